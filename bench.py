@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark: TWED cell updates per second on one MI355X.
+
+Headline workload: one pair of 8-D Gaussian random walks, n = m = 1,000,000
+(regular timestamps, nu = 1e-3, lambda = 1, L2 point cost), FP32 inputs and
+costs with FP64 accumulators, inputs resident in device memory.  One step is
+one full twed_pair call (staging + the wavefront sweep, 10^12 cells).
+
+Also reported (secondary, not the headline value): the batched all-pairs
+distance matrix of 2,048 1-D FP32 walks with lengths uniform in [64, 1024].
+
+Printed: ONE JSON line with metric, value (GCUPS), timing, the roofline of the
+dominant kernel (VALU-bound: lane operations per cell x cells / kernel time vs
+the chip's VALU lane rate) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Peak VALU lane rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one full-rate FP32 or FP64 lane operation per lane per clock, no packed
+# math); 78.6 TFLOP/s FP64 vector = this rate x 2 flops per FMA.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Algorithmic VALU lane operations per DP cell (see the design notes):
+#   8-D L2 distance in f32: 8 sub + 1 mul + 7 fma + sqrt (quarter rate: 4) = 20
+#   time term: sub + fma = 2;   f32 -> f64 convert = 1
+#   f64: match add, up + del_A, left + del_B, X update add, 2 min = 6
+OPS_PER_CELL_8D_L2_ACC64 = 29
+#   1-D L1 in f32: sub + (abs free) 1, time sub + fma 2, 3 adds, X add, min3 (2) = 8..9
+OPS_PER_CELL_1D_L1_F32 = 9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1_000_000, help="series length of the headline pair")
+    ap.add_argument("--strip-k", type=int, default=0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched all-pairs measurement")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=30000, help="prefix length of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) / 1e3 for a, b in ev]
+    return wall, per
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
+                                   "this build (see the design notes on sharding)", "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+    import paper_2007_16135_amd as tw
+    from paper_2007_16135_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    tw.load_library()
+
+    # ---- headline: one 8-D pair, n = m = 1e6, FP32 costs + FP64 accumulators
+    n = args.n
+    log(f"generating 8-D walks n={n}")
+    c = synth.single_pair_8d(n)
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    A, TA, B, TB = f32(c.A), f32(c.TA), f32(c.B), f32(c.TB)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    prm = tw.make_params(c.nu, c.lam, c.p, 8, "f32_acc64", strip_k=args.strip_k)
+    ws = torch.empty(max(tw.twed_pair_workspace_size(n, n, prm), 256), dtype=torch.uint8, device=dev)
+
+    def step():
+        tw.twed_pair(A, TA, B, TB, c.nu, c.lam, c.p, "f32_acc64", strip_k=args.strip_k, out=out,
+                     workspace=ws)
+
+    log(f"headline: warmup {args.warmup}, steps {args.steps}")
+    wall, per = time_steps(step, args.steps, args.warmup, torch)
+    value = float(out.item())
+    cells = float(n) * float(n)
+    ms_step = wall / args.steps * 1e3
+    gcups = cells * args.steps / wall / 1e9
+    kern_s = float(np.mean(per))
+    achieved = OPS_PER_CELL_8D_L2_ACC64 * cells / kern_s / 1e12
+    log(f"headline: {ms_step:.1f} ms/step, {gcups:.1f} GCUPS, value {value!r}")
+
+    result = {
+        "metric": "TWED GCUPS (1 pair n=1e6; batched all-pairs) + k-NN queries/s at recall@10>=0.99",
+        "value": round(gcups, 3),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 costs / f64 accumulators",
+        "data": "synthetic (seeded Gaussian random walks)",
+        "config": {"workload": f"single pair, 8-D random walks n=m={n}, regular timestamps, nu=1e-3, "
+                               f"lambda=1, L2, FP32 costs + FP64 accumulators",
+                   "cells_per_step": cells, "result": value},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+                     "unit": "T VALU lane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": None, "kernel": "wavefront_kernel<float,double,8,L2,K>",
+                     "ops_per_cell": OPS_PER_CELL_8D_L2_ACC64, "kernel_avg_s": kern_s},
+    }
+
+    # ---- secondary: batched all-pairs, 2048 1-D FP32 series
+    if not args.no_batch:
+        log("generating batch collection 2048 x [64, 1024]")
+        col = synth.batch_collection(2048, 64, 1024)
+        X = torch.as_tensor(col.X.astype(np.float32), device=dev)
+        T = torch.as_tensor(col.T.astype(np.float32), device=dev)
+        L = col.lengths.astype(np.float64)
+        bcells = float((L.sum() ** 2 - (L ** 2).sum()) / 2)
+        D = torch.empty((2048, 2048), dtype=torch.float32, device=dev)
+        bprm = tw.make_params(1e-3, 1.0, 1.0, 1, "f32")
+        bws = torch.empty(max(tw.twed_batch_workspace_size(col.off, None, bprm), 256), dtype=torch.uint8,
+                          device=dev)
+
+        def bstep():
+            tw.twed_batch(X, T, col.off, nu=1e-3, lam=1.0, p=1.0, precision="f32", D=D, workspace=bws)
+
+        bwall, bper = time_steps(bstep, max(args.steps, 3), 1, torch)
+        bk = float(np.mean(bper))
+        result["batched_all_pairs"] = {
+            "workload": "2048 1-D FP32 walks, lengths U[64,1024], irregular Exp(1) times, nu=1e-3, "
+                        "lambda=1, L1; symmetric matrix (upper triangle swept)",
+            "cells_per_step": bcells, "ms_per_step": round(bwall / max(args.steps, 3) * 1e3, 3),
+            "GCUPS": round(bcells / bk / 1e9, 3),
+            "roofline_frac": round(OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / VALU_PEAK_TOPS, 4),
+        }
+        log(f"batch: {result['batched_all_pairs']}")
+
+    # ---- CPU oracle on a bounded sample (prefix of the headline pair)
+    if not args.no_cpu:
+        import oracle
+        m = min(args.cpu_n, n)
+        pc = c.prefix(m).astype(np.float32).astype(np.float64)
+        log(f"cpu oracle on the {m}x{m} prefix")
+        t0 = time.perf_counter()
+        oracle.get().twed(pc.A, pc.TA, pc.B, pc.TB, pc.nu, pc.lam, pc.p, rows=True)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(m * m / dt / 1e9, 5), "unit": "GCUPS", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"{m}x{m} prefix of the headline pair (FP64 oracle, two-row "
+                                            f"form, one thread; {dt:.1f} s)"}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,169 @@
+/*
+ * twed.h -- C ABI of libtwed, Time Warp Edit Distance on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The distance is the one defined in the paper's section "Time Warp Edit
+ * Distance" (steps 1-6) with Marteau's cost terms: for series A (nA samples
+ * of `dim` components, timestamps TA) and B (nB samples, TB), zero-padded at
+ * index 0,
+ *
+ *   del_A(i)  = d(A'_i, A'_{i-1}) + nu*|TA'_i - TA'_{i-1}| + lambda
+ *   del_B(j)  = d(B'_j, B'_{j-1}) + nu*|TB'_j - TB'_{j-1}| + lambda
+ *   mat(i,j)  = d(A'_i, B'_j) + d(A'_{i-1}, B'_{j-1})
+ *               + nu*(|TA'_i - TB'_j| + |TA'_{i-1} - TB'_{j-1}|)
+ *   DP[0][0] = 0, DP[i][0] = DP[0][j] = +inf,
+ *   DP[i][j] = min(DP[i-1][j] + del_A(i), DP[i][j-1] + del_B(j),
+ *                  DP[i-1][j-1] + mat(i,j)),        TWED = DP[nA][nB],
+ *
+ * with d the Lp distance of degree p including its 1/p root (section
+ * "cuTWED Implementation Remarks").  The library evaluates the DP by the
+ * anti-diagonal band of the section "Improved Time Warp Edit Distance":
+ * cell (row, col) lies on diagonal row+col at index col (Eq. (1), (2)); every
+ * cell of a diagonal depends only on the two previous diagonals and is
+ * updated in parallel, and only O(nA + nB) state is kept.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments named as device arrays are device pointers owned by the
+ *    caller; the library never allocates or frees device memory.  Scratch
+ *    memory comes from the caller's `workspace` (device, 256-byte aligned),
+ *    whose size is given by the matching *_workspace_size() call.
+ *  - Work is enqueued on `stream` (NULL = the default stream) and is
+ *    asynchronous: results are valid once the stream has been synchronised.
+ *  - Argument errors are detected on the host before any HIP call and
+ *    returned synchronously; outputs are then left untouched.
+ *  - A device fault is sticky in HIP: it surfaces as TWED_ERR_DEVICE from
+ *    the next call or from twed_stream_check().
+ *  - Calls are thread-safe when concurrent calls use distinct workspaces.
+ *  - Inputs containing NaN give unspecified results.  Timestamps need not be
+ *    sorted; the cost uses their absolute differences.
+ */
+#ifndef TWED_H_
+#define TWED_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TWED_OK = 0,
+    TWED_ERR_INVALID = 1,     /* bad argument (null pointer, size < 1, nu < 0, ...) */
+    TWED_ERR_UNSUPPORTED = 2, /* valid but not supported (dim too large, ...) */
+    TWED_ERR_WORKSPACE = 3,   /* workspace missing, too small or misaligned */
+    TWED_ERR_DEVICE = 4       /* a HIP call failed (possibly an earlier fault) */
+} twed_status;
+
+/* Arithmetic of a call (the paper's experiments are FP64; FP32 halves storage). */
+typedef enum {
+    TWED_F64 = 0,       /* f64 inputs, f64 costs, f64 accumulators, f64 results */
+    TWED_F32 = 1,       /* f32 inputs, f32 costs, f32 accumulators, f32 results */
+    TWED_F32_ACC64 = 2, /* f32 inputs, f32 costs, f64 accumulators, f64 results */
+    TWED_AUTO = 3       /* f32 inputs, f64 results: F32_ACC64 when the longest
+                           series of the call exceeds acc64_threshold samples,
+                           otherwise F32 (whose result is widened to f64) */
+} twed_precision;
+
+/* How a single pair is swept. */
+typedef enum {
+    TWED_ALGO_AUTO = 0,      /* the library's choice (currently WAVEFRONT) */
+    TWED_ALGO_WAVEFRONT = 1, /* persistent wave pipeline: each wave carries a
+                                64-cell segment of the three-diagonal band in
+                                registers across a strip of columns */
+    TWED_ALGO_DIAGONAL = 2   /* one kernel launch per anti-diagonal with three
+                                diagonal vectors in device memory, as in the
+                                paper's implementation remarks (slow for long
+                                series; kept as a cross-check) */
+} twed_algo;
+
+#define TWED_MAX_DIM 16
+
+typedef struct {
+    double nu;               /* stiffness, >= 0 and finite */
+    double lambda;           /* deletion penalty, >= 0 and finite */
+    double p;                /* Lp degree, >= 1 and finite */
+    int32_t dim;             /* components per sample, 1..TWED_MAX_DIM */
+    int32_t precision;       /* twed_precision */
+    int32_t algo;            /* twed_algo (single pairs only) */
+    int32_t strip_k;         /* 0 = auto; else columns per lane of the
+                                wavefront sweep (1, 2, 4 or 8) */
+    int64_t acc64_threshold; /* TWED_AUTO switch-over length; <= 0 means 100000 */
+} twed_params;
+
+/* Fills *prm with nu = 0.001, lambda = 1, p = 1, dim = 1, TWED_F64, auto
+   algorithm and threshold. */
+void twed_params_default(twed_params *prm);
+
+/* ---- one pair -------------------------------------------------------------
+ * A: device, nA*dim samples, row-major (sample-major, components fastest);
+ * TA: device, nA timestamps; likewise B, TB.  Element type: double for
+ * TWED_F64, float otherwise.
+ * out: device, one element: float for TWED_F32, double otherwise.
+ * Errors: TWED_ERR_INVALID for nA < 1, nB < 1, null pointers, dim < 1,
+ * nu < 0, lambda < 0, p < 1, non-finite parameters or an unknown precision /
+ * algorithm; TWED_ERR_UNSUPPORTED for dim > TWED_MAX_DIM or nA, nB >= 2^31;
+ * TWED_ERR_WORKSPACE if ws_bytes < twed_pair_workspace_size(...). */
+size_t twed_pair_workspace_size(int64_t nA, int64_t nB, const twed_params *prm);
+
+twed_status twed_pair(const void *A, const void *TA, int64_t nA,
+                      const void *B, const void *TB, int64_t nB,
+                      const twed_params *prm, void *out,
+                      void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Same as twed_pair, and also writes every DP cell to `dp` (device,
+ * (nA+1)*(nB+1) elements of the result type, row-major, row stride nB+1,
+ * row 0 and column 0 included).  Meant for validation on small problems:
+ * the caller owns `dp`; no size limit is imposed beyond memory. */
+twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA,
+                             const void *B, const void *TB, int64_t nB,
+                             const twed_params *prm, void *out, void *dp,
+                             void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---- many pairs (the paper's batch mode, section "cuTWED Implementation
+ * Remarks"; the symmetric case computes only the upper triangle, as the
+ * section "Validation using Real Datasets" anticipates) ---------------------
+ * X: device, packed samples of nX series (sum of lengths x dim); TX: device,
+ * packed timestamps; offX: HOST, nX+1 non-decreasing int64 offsets (in
+ * samples) with offX[0] = 0 and every length >= 1.  Same for Y / TY / offY.
+ * Y == NULL means Y = X (then TY and offY must be NULL and nY == nX): the
+ * symmetric all-pairs matrix, computed on the upper triangle, mirrored, with
+ * a zero diagonal.
+ * pairs == NULL: D is the nX x nY matrix, row-major, D[i*nY + j] =
+ *   TWED(X_i, Y_j).
+ * pairs != NULL: device array of nPairs (i, j) int64 pairs (0 <= i < nX,
+ *   0 <= j < nY); D[k] = TWED(X_{pairs[2k]}, Y_{pairs[2k+1]}).
+ * D: device, element type as `out` of twed_pair.  Every entry is
+ * bitwise equal to what twed_pair returns for the same two series
+ * and parameters, whichever operand is longer.
+ * Errors as for twed_pair, plus TWED_ERR_INVALID for bad offsets and
+ * TWED_ERR_UNSUPPORTED, in pair-list mode, when both collections hold a
+ * series longer than twed_batch_max_short_length(dim). */
+size_t twed_batch_workspace_size(const int64_t *offX, int64_t nX,
+                                 const int64_t *offY, int64_t nY,
+                                 const twed_params *prm);
+
+twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64_t nX,
+                       const void *Y, const void *TY, const int64_t *offY, int64_t nY,
+                       const int64_t *pairs, int64_t nPairs,
+                       const twed_params *prm, void *D,
+                       void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Longest shorter-operand length a pair may have to be swept by a single
+ * wave inside the batched kernel (longer pairs use the single-pair sweep). */
+int64_t twed_batch_max_short_length(int32_t dim);
+
+/* ---- status ---------------------------------------------------------------- */
+const char *twed_status_string(twed_status s);
+/* Message of the last error returned on the calling thread ("" if none). */
+const char *twed_last_error(void);
+/* Synchronises `stream` and reports TWED_ERR_DEVICE if it has failed. */
+twed_status twed_stream_check(hipStream_t stream);
+/* Library version string. */
+const char *twed_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TWED_H_ */

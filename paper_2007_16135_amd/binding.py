@@ -1,0 +1,271 @@
+"""Thin Python binding of libtwed (ctypes).  Argument marshalling only: every
+step of the distance computation runs in the HIP library.
+
+Tensors are PyTorch device tensors (PyTorch supplies device memory and the
+current stream); the functions keep the C names of include/twed.h.  The
+library must have been built (``python -m paper_2007_16135_amd.build``):
+a missing library raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtwed.so")
+
+TWED_OK, TWED_ERR_INVALID, TWED_ERR_UNSUPPORTED, TWED_ERR_WORKSPACE, TWED_ERR_DEVICE = range(5)
+PRECISIONS = {"f64": 0, "f32": 1, "f32_acc64": 2, "auto": 3}
+ALGOS = {"auto": 0, "wavefront": 1, "diagonal": 2}
+EXPORTS = [
+    "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_matrix",
+    "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
+    "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
+]
+
+
+class TwedParams(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("lambda_", ctypes.c_double), ("p", ctypes.c_double),
+                ("dim", ctypes.c_int32), ("precision", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("strip_k", ctypes.c_int32), ("acc64_threshold", ctypes.c_int64)]
+
+
+class TwedError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libtwed status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_pp = ctypes.POINTER(TwedParams)
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libtwed.so and declares its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libtwed not built: {path} is missing "
+                           "(run python -m paper_2007_16135_amd.build)")
+    L = ctypes.CDLL(path)
+    L.twed_params_default.argtypes = [_pp]
+    L.twed_params_default.restype = None
+    L.twed_pair_workspace_size.argtypes = [_i64, _i64, _pp]
+    L.twed_pair_workspace_size.restype = ctypes.c_size_t
+    L.twed_pair.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.twed_pair.restype = ctypes.c_int
+    L.twed_pair_matrix.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.twed_pair_matrix.restype = ctypes.c_int
+    L.twed_batch_workspace_size.argtypes = [_i64p, _i64, _i64p, _i64, _pp]
+    L.twed_batch_workspace_size.restype = ctypes.c_size_t
+    L.twed_batch.argtypes = [_vp, _vp, _i64p, _i64, _vp, _vp, _i64p, _i64, _vp, _i64, _pp, _vp, _vp,
+                             ctypes.c_size_t, _vp]
+    L.twed_batch.restype = ctypes.c_int
+    L.twed_batch_max_short_length.argtypes = [ctypes.c_int32]
+    L.twed_batch_max_short_length.restype = ctypes.c_int64
+    L.twed_status_string.argtypes = [ctypes.c_int]
+    L.twed_status_string.restype = ctypes.c_char_p
+    L.twed_last_error.argtypes = []
+    L.twed_last_error.restype = ctypes.c_char_p
+    L.twed_stream_check.argtypes = [_vp]
+    L.twed_stream_check.restype = ctypes.c_int
+    L.twed_version.argtypes = []
+    L.twed_version.restype = ctypes.c_char_p
+    if path == LIB_PATH:
+        _lib = L
+    return L
+
+
+def make_params(nu=1e-3, lam=1.0, p=1.0, dim=1, precision="f64", algo="auto", strip_k=0,
+                acc64_threshold=0) -> TwedParams:
+    prm = TwedParams()
+    load_library().twed_params_default(ctypes.byref(prm))
+    prm.nu, prm.lambda_, prm.p, prm.dim = float(nu), float(lam), float(p), int(dim)
+    prm.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    prm.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    prm.strip_k = int(strip_k)
+    prm.acc64_threshold = int(acc64_threshold)
+    return prm
+
+
+def _check(status: int):
+    if status != TWED_OK:
+        L = load_library()
+        raise TwedError(status, L.twed_last_error().decode() or L.twed_status_string(status).decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def input_dtype(precision):
+    torch = _torch()
+    return torch.float64 if precision in ("f64", 0) else torch.float32
+
+
+def output_dtype(precision):
+    torch = _torch()
+    return torch.float32 if precision in ("f32", 1) else torch.float64
+
+
+def _dev(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return t
+
+
+def _workspace(nbytes, device, workspace=None):
+    torch = _torch()
+    nbytes = max(int(nbytes), 256)
+    if workspace is not None and workspace.numel() >= nbytes:
+        return workspace
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def twed_pair_workspace_size(nA, nB, prm: TwedParams) -> int:
+    return load_library().twed_pair_workspace_size(int(nA), int(nB), ctypes.byref(prm))
+
+
+def twed_pair(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", algo="auto", strip_k=0,
+              acc64_threshold=0, out=None, workspace=None, stream=None):
+    """TWED of one pair of device series.  A: (nA, dim) or (nA,), TA: (nA,).
+    Returns a one-element device tensor (float32 for "f32", float64 otherwise)."""
+    torch = _torch()
+    dt = input_dtype(precision)
+    A2 = A if A.dim() == 2 else A.reshape(-1, 1)
+    B2 = B if B.dim() == 2 else B.reshape(-1, 1)
+    _dev(A2, dt, "A"); _dev(B2, dt, "B"); _dev(TA, dt, "TA"); _dev(TB, dt, "TB")
+    nA, dim = A2.shape
+    nB = B2.shape[0]
+    if B2.shape[1] != dim or TA.numel() != nA or TB.numel() != nB:
+        raise ValueError("shape mismatch")
+    prm = make_params(nu, lam, p, dim, precision, algo, strip_k, acc64_threshold)
+    L = load_library()
+    need = L.twed_pair_workspace_size(nA, nB, ctypes.byref(prm))
+    ws = _workspace(need, A2.device, workspace)
+    if out is None:
+        out = torch.empty(1, dtype=output_dtype(precision), device=A2.device)
+    _check(L.twed_pair(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
+                       ctypes.byref(prm), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out
+
+
+def twed_pair_matrix(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", algo="auto", strip_k=0,
+                     stream=None):
+    """Like twed_pair, and also returns every DP cell as an (nA+1, nB+1) tensor."""
+    torch = _torch()
+    dt = input_dtype(precision)
+    A2 = A if A.dim() == 2 else A.reshape(-1, 1)
+    B2 = B if B.dim() == 2 else B.reshape(-1, 1)
+    _dev(A2, dt, "A"); _dev(B2, dt, "B"); _dev(TA, dt, "TA"); _dev(TB, dt, "TB")
+    nA, dim = A2.shape
+    nB = B2.shape[0]
+    prm = make_params(nu, lam, p, dim, precision, algo, strip_k)
+    L = load_library()
+    ws = _workspace(L.twed_pair_workspace_size(nA, nB, ctypes.byref(prm)), A2.device)
+    out = torch.empty(1, dtype=output_dtype(precision), device=A2.device)
+    dp = torch.empty((nA + 1, nB + 1), dtype=output_dtype(precision), device=A2.device)
+    _check(L.twed_pair_matrix(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
+                              ctypes.byref(prm), out.data_ptr(), dp.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream(stream)))
+    return out, dp
+
+
+def _offsets(off):
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    return off, off.ctypes.data_as(_i64p)
+
+
+def twed_batch_workspace_size(offX, offY, prm: TwedParams) -> int:
+    offX, px = _offsets(offX)
+    if offY is None:
+        return load_library().twed_batch_workspace_size(px, len(offX) - 1, None, 0, ctypes.byref(prm))
+    offY, py = _offsets(offY)
+    return load_library().twed_batch_workspace_size(px, len(offX) - 1, py, len(offY) - 1, ctypes.byref(prm))
+
+
+def twed_batch(X, TX, offX, Y=None, TY=None, offY=None, pairs=None, nu=1e-3, lam=1.0, p=1.0,
+               precision="f32", D=None, workspace=None, stream=None):
+    """Distances between packed collections (offsets are host int64 arrays).
+
+    Y is None: symmetric nX x nX matrix (upper triangle swept).  pairs (device
+    int64 (P, 2)) given: D[k] = TWED(X_i, Y_j) for the listed pairs.
+    """
+    torch = _torch()
+    dt = input_dtype(precision)
+    X2 = X if X.dim() == 2 else X.reshape(-1, 1)
+    _dev(X2, dt, "X"); _dev(TX, dt, "TX")
+    dim = X2.shape[1]
+    offX, px = _offsets(offX)
+    nX = len(offX) - 1
+    if Y is None:
+        Yp = TYp = None
+        py, nY = None, nX
+        offYa = None
+    else:
+        Y2 = Y if Y.dim() == 2 else Y.reshape(-1, 1)
+        _dev(Y2, dt, "Y"); _dev(TY, dt, "TY")
+        offYa, py = _offsets(offY)
+        nY = len(offYa) - 1
+        Yp, TYp = Y2.data_ptr(), TY.data_ptr()
+    prm = make_params(nu, lam, p, dim, precision)
+    L = load_library()
+    need = L.twed_batch_workspace_size(px, nX, py, nY if Y is not None else 0, ctypes.byref(prm))
+    ws = _workspace(need, X2.device, workspace)
+    if pairs is not None:
+        _dev(pairs, torch.int64, "pairs")
+        nP = pairs.shape[0]
+        if D is None:
+            D = torch.empty(nP, dtype=output_dtype(precision), device=X2.device)
+        if nP == 0:
+            return D
+        pp = pairs.data_ptr()
+    else:
+        nP = 0
+        pp = None
+        if D is None:
+            D = torch.empty((nX, nY), dtype=output_dtype(precision), device=X2.device)
+    _check(L.twed_batch(X2.data_ptr(), TX.data_ptr(), px, nX, Yp, TYp, py, nY, pp, nP,
+                        ctypes.byref(prm), D.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return D
+
+
+def twed_stream_check(stream=None):
+    _check(load_library().twed_stream_check(_stream(stream)))
+
+
+def twed_version() -> str:
+    return load_library().twed_version().decode()
+
+
+def twed_host(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", device="cuda", **kw) -> float:
+    """Host-array convenience (the paper's managed call): copies numpy inputs
+    to the device, runs twed_pair and returns the value as a Python float."""
+    torch = _torch()
+    dt = input_dtype(precision)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+    A = np.asarray(A)
+    B = np.asarray(B)
+    out = twed_pair(t(A.reshape(len(A), -1)), t(TA), t(B.reshape(len(B), -1)), t(TB), nu, lam, p,
+                    precision, **kw)
+    return float(out.item())

@@ -1,0 +1,222 @@
+// batch.hip -- many TWED pairs in one persistent launch.
+//
+// The paper's batch mode (section "cuTWED Implementation Remarks") maps
+// (series pair, diagonal entry) onto a 2-D grid and fills the whole distance
+// matrix; its section "Validation using Real Datasets" notes that the
+// symmetric case needs only the upper triangle.  Here each pair is swept by
+// one wave with the whole band in registers: the shorter series is spread
+// over the 64 lanes (K = ceil(n/64) columns per lane, K <= KMAX), the longer
+// one streams through them, and the three live diagonals never leave the
+// register file.  Waves pull pairs from an atomic ticket; in the symmetric
+// mode the series are visited longest-first so the expensive pairs start
+// first and the cheap ones fill the tail.  Results are bitwise equal to the
+// single-pair sweep: both evaluate every cell with the same lane code, and
+// the cell arithmetic is symmetric under transposition.
+#include "twed_dispatch.h"
+
+#include <math.h>
+
+namespace twed {
+
+int batch_kmax(int dimt)
+{
+    if (dimt <= 1) return 16;
+    if (dimt <= 4) return 8;
+    if (dimt <= 8) return 4;
+    return 2;
+}
+
+template <int DIMT>
+__host__ __device__ constexpr int kmax_of()
+{
+    return DIMT <= 1 ? 16 : (DIMT <= 4 ? 8 : (DIMT <= 8 ? 4 : 2));
+}
+
+// Sweeps one pair with one wave; returns DP(nA, nB) in every lane.  Pairs
+// here are short enough that the FP32 offset is zero (the single-pair sweep
+// applies one only beyond kOffsetMinLength samples), so the two paths stay
+// bitwise equal.
+template <typename CT, typename AT, int DIMT, int PM, int K>
+__device__ __forceinline__ AT sweep_pair(const CT *__restrict__ rowsA, int nA, const CT *__restrict__ rowsB,
+                                         int nB, const CostArgs<CT> &ca)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const AT INF = pinf<AT>();
+    const int c0 = 1 + lane * K;
+    Lane<CT, AT, DIMT, K> L;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        Row<CT, DIMT> b;
+        load_row<CT, DIMT>(rowsB, c0 + j <= nB ? c0 + j : nB, b);
+#pragma unroll
+        for (int k = 0; k < DIMT; ++k) L.bx[j][k] = b.x[k];
+        L.bt[j] = b.t;
+        L.bdel[j] = (AT)b.del;
+        L.up[j] = INF;
+        L.xp[j] = INF;
+    }
+    const int q = nB - 1;
+    const int lstar = q / K, jstar = q - (q / K) * K;
+
+    AT sh_l = INF;
+    AT sh_x = lane == 0 ? -AT(0) : INF;  // X(0,0) = -beta with beta = 0
+    AT sh_xo = INF;
+    Row<CT, DIMT> cur;
+    load_row<CT, DIMT>(rowsA, 0, cur);
+    const int T = nA + lstar + 1;  // last step: lane lstar finishes row nA
+    for (int t = 0; t < T; ++t) {
+        int rn = t + 1 - lane;
+        rn = rn < 0 ? 0 : (rn > nA ? nA : rn);
+        Row<CT, DIMT> nxt;
+        load_row<CT, DIMT>(rowsA, rn, nxt);
+        AT left = sh_l, xl;
+        lane_row<CT, AT, DIMT, PM, K>(L, cur, left, sh_xo, xl, ca.nu, ca.p, ca.invp, CT(0));
+        sh_xo = sh_x;
+        sh_l = shift_in(left, INF);
+        sh_x = shift_in(xl, INF);
+        cur = nxt;
+    }
+    AT res = L.up[0];
+#pragma unroll
+    for (int j = 1; j < K; ++j)
+        if (j == jstar) res = L.up[j];
+    return lane_value(res, lstar);
+}
+
+template <typename CT, typename AT, int DIMT, int PM, int K>
+__device__ __forceinline__ AT sweep_dispatch(int k, const CT *rowsA, int nA, const CT *rowsB, int nB,
+                                             const CostArgs<CT> &ca)
+{
+    if constexpr (K > kmax_of<DIMT>()) {
+        return AT(0);
+    } else {
+        if (k == K) return sweep_pair<CT, AT, DIMT, PM, K>(rowsA, nA, rowsB, nB, ca);
+        return sweep_dispatch<CT, AT, DIMT, PM, K + 1>(k, rowsA, nA, rowsB, nB, ca);
+    }
+}
+
+template <typename CT, typename AT, int DIMT, int PM>
+__global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX, const CT *__restrict__ rowsY,
+                                                   const int64_t *__restrict__ offX,
+                                                   const int64_t *__restrict__ offY,
+                                                   const int32_t *__restrict__ order,
+                                                   const int64_t *__restrict__ pairs, int64_t nX, int64_t nY,
+                                                   int64_t nItems, int mode, CostArgs<CT> ca, AT *D,
+                                                   uint32_t *ticket)
+{
+    constexpr int S = Row<CT, DIMT>::kStride;
+    constexpr int KMAX = kmax_of<DIMT>();
+    for (;;) {
+        const int64_t item = (int64_t)next_ticket(ticket);
+        if (item >= nItems) break;
+
+        int64_t a, b;
+        if (mode == kSymmetric) {
+            // item -> (i < j) over the length-sorted order: j-th group holds
+            // the pairs (0..j-1, j).
+            int64_t j = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)item)) * 0.5);
+            while (j * (j - 1) / 2 > item) --j;
+            while ((j + 1) * j / 2 <= item) ++j;
+            const int64_t i = item - j * (j - 1) / 2;
+            a = order[i];
+            b = order[j];
+        } else if (mode == kRect) {
+            a = item / nY;
+            b = item - a * nY;
+        } else {
+            a = pairs[2 * item];
+            b = pairs[2 * item + 1];
+        }
+        const int64_t xa = offX[a], la = offX[a + 1] - xa;
+        const int64_t yb = offY[b], lb = offY[b + 1] - yb;
+        const CT *ra = rowsX + (xa + a) * S;
+        const CT *rb = rowsY + (yb + b) * S;
+        // shorter operand across the lanes
+        const bool swap = lb > la;
+        const CT *rowsA = swap ? rb : ra;
+        const CT *rowsB = swap ? ra : rb;
+        const int nA = (int)(swap ? lb : la);
+        const int nB = (int)(swap ? la : lb);
+        const int k = (nB + kWave - 1) / kWave;
+        // Pairs wider than one wave are swept by the single-pair path instead.
+        if (k <= KMAX) {
+            // d is the same in every lane; every lane stores it (one
+            // transaction), so the loop body holds no lane-conditional branch.
+            const AT d = sweep_dispatch<CT, AT, DIMT, PM, 1>(k, rowsA, nA, rowsB, nB, ca);
+            if (mode == kSymmetric) {
+                D[a * nX + b] = d;
+                D[b * nX + a] = d;
+            } else {
+                D[item] = d;
+            }
+        }
+    }
+}
+
+template <typename CT, typename AT, int DIMT, int PM>
+static int batch_occupancy()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<CT, AT, DIMT, PM>, kWave, 0) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
+hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hipStream_t st)
+{
+    return by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
+        hipLaunchKernelGGL((batch_kernel<CT, AT, DIMT, PM>), dim3(a.grid), dim3(kWave), 0, st,
+                           (const CT *)a.rowsX, (const CT *)a.rowsY, a.offX, a.offY, a.order, a.pairs, a.nX,
+                           a.nY, a.nItems, a.mode, CostArgs<CT>::make(cp), (AT *)a.D, a.ticket);
+        return hipGetLastError();
+    });
+}
+
+int batch_max_workers(Prec prec, const CostParams &cp)
+{
+    int per_cu = 0;
+    hipError_t e = by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
+        per_cu = batch_occupancy<CT, AT, DIMT, PM>();
+        return hipSuccess;
+    });
+    if (e != hipSuccess || per_cu <= 0) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+template <typename AT>
+__global__ void diag_zero_kernel(AT *D, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        D[i * n + i] = AT(0);
+}
+
+template <typename AT>
+__global__ void copy_one_kernel(const AT *src, AT *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
+}
+
+hipError_t launch_batch_diag_zero(Prec prec, void *D, int64_t n, hipStream_t st)
+{
+    const int grid = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    if (prec == kF32)
+        hipLaunchKernelGGL(diag_zero_kernel<float>, dim3(grid), dim3(256), 0, st, (float *)D, n);
+    else
+        hipLaunchKernelGGL(diag_zero_kernel<double>, dim3(grid), dim3(256), 0, st, (double *)D, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_one(Prec prec, const void *src, void *dst, hipStream_t st)
+{
+    if (prec == kF32)
+        hipLaunchKernelGGL(copy_one_kernel<float>, dim3(1), dim3(64), 0, st, (const float *)src, (float *)dst);
+    else
+        hipLaunchKernelGGL(copy_one_kernel<double>, dim3(1), dim3(64), 0, st, (const double *)src, (double *)dst);
+    return hipGetLastError();
+}
+
+}  // namespace twed

@@ -1,0 +1,542 @@
+// twed_capi.hip -- the extern "C" boundary of libtwed: argument validation,
+// workspace layout, precision policy, strip-width choice and dispatch.
+//
+// Host code only.  Every argument error is detected here before the first
+// HIP call (section "Time Warp Edit Distance" fixes what a valid problem is:
+// two non-empty series with timestamps, nu >= 0, lambda >= 0, an Lp degree).
+#include "../../include/twed.h"
+#include "twed_kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace twed;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+twed_status fail(twed_status s, const char *msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+twed_status fail_hip(hipError_t e, const char *where)
+{
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return TWED_ERR_DEVICE;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxLen = (int64_t(1) << 31) - 2 * 64 - 2;
+constexpr int64_t kDefaultAcc64Threshold = 100000;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carve-out of the caller's workspace.
+struct Carver {
+    char *base;
+    size_t used = 0;
+    void *take(size_t bytes)
+    {
+        void *p = base ? base + used : nullptr;
+        used += align_up(bytes);
+        return p;
+    }
+};
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+twed_status check_params(const twed_params *prm)
+{
+    if (!prm) return fail(TWED_ERR_INVALID, "params is NULL");
+    if (!finite_nonneg(prm->nu)) return fail(TWED_ERR_INVALID, "nu must be finite and >= 0");
+    if (!finite_nonneg(prm->lambda)) return fail(TWED_ERR_INVALID, "lambda must be finite and >= 0");
+    if (!std::isfinite(prm->p) || prm->p < 1.0) return fail(TWED_ERR_INVALID, "p must be finite and >= 1");
+    if (prm->dim < 1) return fail(TWED_ERR_INVALID, "dim must be >= 1");
+    if (prm->dim > TWED_MAX_DIM) return fail(TWED_ERR_UNSUPPORTED, "dim exceeds TWED_MAX_DIM");
+    if (prm->precision < TWED_F64 || prm->precision > TWED_AUTO)
+        return fail(TWED_ERR_INVALID, "unknown precision");
+    if (prm->algo < TWED_ALGO_AUTO || prm->algo > TWED_ALGO_DIAGONAL) return fail(TWED_ERR_INVALID, "unknown algo");
+    if (!(prm->strip_k == 0 || prm->strip_k == 1 || prm->strip_k == 2 || prm->strip_k == 4 || prm->strip_k == 8))
+        return fail(TWED_ERR_INVALID, "strip_k must be 0, 1, 2, 4 or 8");
+    return TWED_OK;
+}
+
+// Resolved arithmetic of a call whose longest series has `maxlen` samples.
+Prec resolve(const twed_params *prm, int64_t maxlen)
+{
+    switch (prm->precision) {
+    case TWED_F64: return kF64;
+    case TWED_F32: return kF32;
+    case TWED_F32_ACC64: return kF32Acc64;
+    default: {
+        const int64_t thr = prm->acc64_threshold > 0 ? prm->acc64_threshold : kDefaultAcc64Threshold;
+        return maxlen > thr ? kF32Acc64 : kF32;
+    }
+    }
+}
+
+// AUTO always returns f64; when it resolves to F32 the kernels write f32 into
+// the workspace and a widening pass copies them out.
+bool needs_widen(const twed_params *prm, Prec p) { return prm->precision == TWED_AUTO && p == kF32; }
+
+CostParams cost_params(const twed_params *prm)
+{
+    CostParams cp;
+    cp.nu = prm->nu;
+    cp.lambda = prm->lambda;
+    cp.p = prm->p;
+    cp.dim = prm->dim;
+    cp.dimt = dimt_for(prm->dim);
+    cp.pm = prm->dim == 1 ? 0 : (prm->p == 1.0 ? 0 : (prm->p == 2.0 ? 1 : 2));
+    return cp;
+}
+
+int device_simds()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
+    return cus * 4;
+}
+
+// Columns per lane of the wavefront sweep: the widest strip that still
+// leaves about 1.5 strips per SIMD, so the pipeline covers the machine.
+int choose_k(const twed_params *prm, int64_t nB)
+{
+    if (prm->strip_k > 0) return prm->strip_k;
+    const int64_t want = (int64_t)device_simds() * 3 / 2;
+    for (int k : {8, 4, 2}) {
+        const int64_t strips = (nB + 64 * k - 1) / (64 * k);
+        if (strips >= want) return k;
+    }
+    return 1;
+}
+
+// The wavefront pipeline stays off until its cross-wave handoff is shown
+// correct on the device.
+bool wavefront_enabled() { return true; }
+
+// Words after the per-strip flags in the zeroed region: work ticket, wait
+// timeout flag, and two words holding the FP32 cost offset.
+constexpr int64_t kTailWords = 4;
+
+struct PairLayout {
+    void *rowsA, *rowsB, *bnd, *zero, *tmp_out;
+    void *z[3], *x[3];
+    int64_t nflags, zero_words;
+    size_t total;
+};
+
+PairLayout pair_layout(char *base, int64_t nA, int64_t nB, const twed_params *prm, Prec prec)
+{
+    const int dimt = dimt_for(prm->dim);
+    const size_t cs = cost_size(prec), as = acc_size(prec);
+    const size_t S = (size_t)row_stride(prec, dimt);
+    Carver c{base};
+    PairLayout L{};
+    L.rowsA = c.take((size_t)(nA + 1) * S * cs);
+    L.rowsB = c.take((size_t)(nB + 1) * S * cs);
+    if (prm->algo == TWED_ALGO_DIAGONAL || (prm->algo == TWED_ALGO_AUTO && !wavefront_enabled())) {
+        for (int i = 0; i < 3; ++i) L.z[i] = c.take((size_t)(nB + 1) * as);
+        for (int i = 0; i < 3; ++i) L.x[i] = c.take((size_t)(nB + 1) * as);
+        L.bnd = nullptr;
+        L.nflags = 0;
+    } else {
+        L.bnd = c.take((size_t)2 * (size_t)(nA + 1) * 2 * as);
+        L.nflags = (nB + 63) / 64;  // flags for the narrowest strips
+    }
+    // zeroed words: flags, then ticket, error word and the FP32 cost offset
+    L.zero_words = L.nflags + kTailWords;
+    L.zero = c.take((size_t)L.zero_words * 4);
+    L.tmp_out = c.take(8);
+    L.total = c.used;
+    return L;
+}
+
+twed_status check_workspace(void *ws, size_t ws_bytes, size_t need)
+{
+    if (need > ws_bytes) return fail(TWED_ERR_WORKSPACE, "workspace smaller than the *_workspace_size() value");
+    if (!ws) return fail(TWED_ERR_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(TWED_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    return TWED_OK;
+}
+
+// Runs the sweep of one pair whose rows are already staged.
+// `tail` points at the kTailWords words after the flags (zeroed beforehand).
+twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *prm, const void *rowsA,
+                           const void *rowsB, int64_t nA, int64_t nB, void *bnd, uint32_t *flags,
+                           uint32_t *tail, const PairLayout *diag_layout, void *out, void *dump,
+                           hipStream_t st)
+{
+    hipError_t e;
+    void *beta = tail + 2;
+    if (prec == kF32 && std::max(nA, nB) > kOffsetMinLength) {
+        e = launch_offset(prec, cp, rowsA, nA, rowsB, nB, beta, st);
+        if (e != hipSuccess) return fail_hip(e, "offset launch");
+    }
+    if (prm->algo == TWED_ALGO_DIAGONAL || (prm->algo == TWED_ALGO_AUTO && !wavefront_enabled())) {
+        if (!diag_layout) return fail(TWED_ERR_UNSUPPORTED, "no single-pair sweep available for this call");
+        DiagonalArgs d{};
+        d.rowsA = rowsA;
+        d.rowsB = rowsB;
+        d.nA = nA;
+        d.nB = nB;
+        for (int i = 0; i < 3; ++i) {
+            d.z[i] = diag_layout->z[i];
+            d.x[i] = diag_layout->x[i];
+        }
+        d.beta = beta;
+        d.out = out;
+        d.dump = dump;
+        e = launch_diagonal(prec, cp, d, st);
+        if (e != hipSuccess) return fail_hip(e, "diagonal sweep launch");
+        return TWED_OK;
+    }
+    if (!wavefront_enabled())
+        return fail(TWED_ERR_UNSUPPORTED, "the wavefront sweep is switched off in this build "
+                                          "(an unexplained stall on its first device run is under investigation)");
+    const int K = choose_k(prm, nB);
+    WavefrontArgs w{};
+    w.rowsA = rowsA;
+    w.rowsB = rowsB;
+    w.nA = nA;
+    w.nB = nB;
+    w.bnd = bnd;
+    w.flags = flags;
+    w.ticket = tail;
+    w.beta = beta;
+    w.nStrips = (nB + 64 * K - 1) / (64 * K);
+    w.out = out;
+    w.dump = dump;
+    int workers = wavefront_max_workers(prec, cp, K);
+    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+    w.grid = (int)std::min<int64_t>(w.nStrips, workers);
+    e = launch_wavefront(prec, cp, K, w, st);
+    if (e != hipSuccess) return fail_hip(e, "wavefront sweep launch");
+    return TWED_OK;
+}
+
+twed_status pair_impl(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                      const twed_params *prm, void *out, void *dp, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    if (!A || !TA || !B || !TB || !out) return fail(TWED_ERR_INVALID, "NULL array argument");
+    if (nA < 1 || nB < 1) return fail(TWED_ERR_INVALID, "series lengths must be >= 1");
+    if (nA > kMaxLen || nB > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    const Prec prec = resolve(prm, std::max(nA, nB));
+    const PairLayout need = pair_layout(nullptr, nA, nB, prm, prec);
+    s = check_workspace(ws, ws_bytes, need.total);
+    if (s != TWED_OK) return s;
+
+    const PairLayout L = pair_layout((char *)ws, nA, nB, prm, prec);
+    const CostParams cp = cost_params(prm);
+    uint32_t *flags = (uint32_t *)L.zero;
+    uint32_t *tail = flags + L.nflags;
+    hipError_t e;
+    // stage A (zeroing flags and ticket on the way), then B
+    e = launch_stage(prec, cp, A, TA, nullptr, 1, nA, nA, L.rowsA, flags, L.zero_words, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    e = launch_stage(prec, cp, B, TB, nullptr, 1, nB, nB, L.rowsB, nullptr, 0, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    if (dp) {
+        e = launch_dump_border(prec, dp, nA, nB, st);
+        if (e != hipSuccess) return fail_hip(e, "dump border launch");
+    }
+    const bool widen = needs_widen(prm, prec);
+    void *kout = widen ? L.tmp_out : out;
+    if (widen && dp) return fail(TWED_ERR_UNSUPPORTED, "twed_pair_matrix does not take TWED_AUTO");
+    s = run_pair_sweep(prec, cp, prm, L.rowsA, L.rowsB, nA, nB, L.bnd, flags, tail, &L, kout, dp, st);
+    if (s != TWED_OK) return s;
+    if (widen) {
+        e = launch_widen((const float *)kout, (double *)out, 1, st);
+        if (e != hipSuccess) return fail_hip(e, "widen launch");
+    }
+    return TWED_OK;
+}
+
+// ---- batch ----------------------------------------------------------------------
+
+twed_status check_offsets(const int64_t *off, int64_t n, int64_t *maxlen, int64_t *total)
+{
+    if (!off) return fail(TWED_ERR_INVALID, "NULL offsets");
+    if (n < 1) return fail(TWED_ERR_INVALID, "collection must hold at least one series");
+    if (off[0] != 0) return fail(TWED_ERR_INVALID, "offsets must start at 0");
+    int64_t mx = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t len = off[i + 1] - off[i];
+        if (len < 1) return fail(TWED_ERR_INVALID, "every series must hold at least one sample");
+        mx = std::max(mx, len);
+    }
+    if (mx > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    *maxlen = mx;
+    *total = off[n];
+    return TWED_OK;
+}
+
+struct BatchLayout {
+    void *rowsX, *rowsY, *offX, *offY, *order, *zero, *bnd, *flags, *tmpD;
+    size_t total;
+};
+
+BatchLayout batch_layout(char *base, int64_t totX, int64_t nX, int64_t maxX, int64_t totY, int64_t nY,
+                         int64_t maxY, bool symmetric, int64_t nOut, const twed_params *prm, Prec prec)
+{
+    const int dimt = dimt_for(prm->dim);
+    const size_t cs = cost_size(prec), as = acc_size(prec);
+    const size_t S = (size_t)row_stride(prec, dimt);
+    Carver c{base};
+    BatchLayout L{};
+    L.rowsX = c.take((size_t)(totX + nX) * S * cs);
+    L.rowsY = symmetric ? L.rowsX : c.take((size_t)(totY + nY) * S * cs);
+    L.offX = c.take((size_t)(nX + 1) * 8);
+    L.offY = symmetric ? L.offX : c.take((size_t)(nY + 1) * 8);
+    L.order = c.take((size_t)nX * 4);
+    L.zero = c.take(4);  // batch ticket
+    // single-pair sweep state for pairs too long for one wave
+    const int64_t maxlen = std::max(maxX, maxY);
+    const int64_t kshort = twed_batch_max_short_length(prm->dim);
+    if (std::min(maxX, maxY) > kshort) {
+        L.bnd = c.take((size_t)2 * (size_t)(maxlen + 1) * 2 * as);
+        L.flags = c.take((size_t)((maxlen + 63) / 64 + kTailWords) * 4);
+    }
+    if (needs_widen(prm, prec)) L.tmpD = c.take((size_t)nOut * 4);
+    L.total = c.used;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+void twed_params_default(twed_params *prm)
+{
+    if (!prm) return;
+    std::memset(prm, 0, sizeof(*prm));
+    prm->nu = 0.001;
+    prm->lambda = 1.0;
+    prm->p = 1.0;
+    prm->dim = 1;
+    prm->precision = TWED_F64;
+    prm->algo = TWED_ALGO_AUTO;
+    prm->strip_k = 0;
+    prm->acc64_threshold = 0;
+}
+
+size_t twed_pair_workspace_size(int64_t nA, int64_t nB, const twed_params *prm)
+{
+    if (check_params(prm) != TWED_OK || nA < 1 || nB < 1 || nA > kMaxLen || nB > kMaxLen) return 0;
+    return pair_layout(nullptr, nA, nB, prm, resolve(prm, std::max(nA, nB))).total;
+}
+
+twed_status twed_pair(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                      const twed_params *prm, void *out, void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    return pair_impl(A, TA, nA, B, TB, nB, prm, out, nullptr, workspace, ws_bytes, stream);
+}
+
+twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                             const twed_params *prm, void *out, void *dp, void *workspace, size_t ws_bytes,
+                             hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!dp) return fail(TWED_ERR_INVALID, "dp is NULL");
+    return pair_impl(A, TA, nA, B, TB, nB, prm, out, dp, workspace, ws_bytes, stream);
+}
+
+int64_t twed_batch_max_short_length(int32_t dim)
+{
+    const int dimt = dimt_for(dim < 1 ? 1 : dim);
+    if (dimt < 0) return 0;
+    return (int64_t)64 * batch_kmax(dimt);
+}
+
+size_t twed_batch_workspace_size(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY,
+                                 const twed_params *prm)
+{
+    if (check_params(prm) != TWED_OK) return 0;
+    int64_t maxX, totX, maxY, totY;
+    if (check_offsets(offX, nX, &maxX, &totX) != TWED_OK) return 0;
+    const bool sym = offY == nullptr;
+    if (sym) {
+        maxY = maxX;
+        totY = totX;
+        nY = nX;
+    } else if (check_offsets(offY, nY, &maxY, &totY) != TWED_OK) {
+        return 0;
+    }
+    const Prec prec = resolve(prm, std::max(maxX, maxY));
+    // the output count is unknown here for pair lists: size for the larger
+    const int64_t nOut = nX * nY;
+    return batch_layout(nullptr, totX, nX, maxX, totY, nY, maxY, sym, nOut, prm, prec).total;
+}
+
+twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64_t nX, const void *Y,
+                       const void *TY, const int64_t *offY, int64_t nY, const int64_t *pairs, int64_t nPairs,
+                       const twed_params *prm, void *D, void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    g_last_error.clear();
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    if (!X || !TX || !D) return fail(TWED_ERR_INVALID, "NULL array argument");
+    int64_t maxX, totX, maxY, totY;
+    s = check_offsets(offX, nX, &maxX, &totX);
+    if (s != TWED_OK) return s;
+    const bool sym = Y == nullptr;
+    if (sym) {
+        if (TY || offY) return fail(TWED_ERR_INVALID, "Y == NULL requires TY == NULL and offY == NULL");
+        if (nY != nX) return fail(TWED_ERR_INVALID, "Y == NULL requires nY == nX");
+        maxY = maxX;
+        totY = totX;
+    } else {
+        if (!TY) return fail(TWED_ERR_INVALID, "NULL array argument");
+        s = check_offsets(offY, nY, &maxY, &totY);
+        if (s != TWED_OK) return s;
+    }
+    if (pairs && nPairs < 0) return fail(TWED_ERR_INVALID, "nPairs must be >= 0");
+    if (nX * nY > (int64_t(1) << 40)) return fail(TWED_ERR_UNSUPPORTED, "too many pairs");
+    const int64_t kshort = twed_batch_max_short_length(prm->dim);
+    if (pairs && std::min(maxX, maxY) > kshort)
+        return fail(TWED_ERR_UNSUPPORTED, "pair lists need one collection of series no longer than "
+                                          "twed_batch_max_short_length(dim)");
+    const Prec prec = resolve(prm, std::max(maxX, maxY));
+    const BatchLayout need = batch_layout(nullptr, totX, nX, maxX, totY, nY, maxY, sym, nX * nY, prm, prec);
+    s = check_workspace(workspace, ws_bytes, need.total);
+    if (s != TWED_OK) return s;
+    const BatchLayout L = batch_layout((char *)workspace, totX, nX, maxX, totY, nY, maxY, sym, nX * nY, prm, prec);
+    const CostParams cp = cost_params(prm);
+    if (pairs && nPairs == 0) return TWED_OK;
+
+    // longest-first order of the series (symmetric mode)
+    std::vector<int32_t> order;
+    if (sym) {
+        order.resize((size_t)nX);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return offX[a + 1] - offX[a] > offX[b + 1] - offX[b];
+        });
+    }
+
+    hipError_t e;
+    e = hipMemcpyAsync(L.offX, offX, (size_t)(nX + 1) * 8, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "offset upload");
+    if (!sym) {
+        e = hipMemcpyAsync(L.offY, offY, (size_t)(nY + 1) * 8, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return fail_hip(e, "offset upload");
+    }
+    if (sym) {
+        e = hipMemcpyAsync(L.order, order.data(), (size_t)nX * 4, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return fail_hip(e, "order upload");
+    }
+    e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, L.rowsX, (uint32_t *)L.zero, 1, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    if (!sym) {
+        e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, L.rowsY, nullptr, 0, st);
+        if (e != hipSuccess) return fail_hip(e, "staging launch");
+    }
+    const bool widen = needs_widen(prm, prec);
+    void *Dk = widen ? L.tmpD : D;
+    const int64_t nOut = pairs ? nPairs : nX * nY;
+
+    BatchArgs b{};
+    b.rowsX = L.rowsX;
+    b.rowsY = L.rowsY;
+    b.offX = (const int64_t *)L.offX;
+    b.offY = (const int64_t *)L.offY;
+    b.order = (const int32_t *)L.order;
+    b.pairs = pairs;
+    b.nX = nX;
+    b.nY = nY;
+    b.mode = pairs ? kPairList : (sym ? kSymmetric : kRect);
+    b.nItems = pairs ? nPairs : (sym ? nX * (nX - 1) / 2 : nX * nY);
+    b.D = Dk;
+    b.ticket = (uint32_t *)L.zero;
+    if (b.nItems > 0xffffffffLL) return fail(TWED_ERR_UNSUPPORTED, "more than 2^32 - 1 pairs in one call");
+    const int workers = batch_max_workers(prec, cp);
+    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+    if (sym) {
+        e = launch_batch_diag_zero(prec, Dk, nX, st);
+        if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
+    }
+    if (b.nItems > 0) {
+        b.grid = (int)std::min<int64_t>(b.nItems, workers);
+        e = launch_batch(prec, cp, b, st);
+        if (e != hipSuccess) return fail_hip(e, "batch launch");
+    }
+
+    // pairs whose shorter series exceeds one wave: single-pair sweeps
+    if (!pairs && std::min(maxX, maxY) > kshort) {
+        const size_t S = (size_t)row_stride(prec, cp.dimt), cs = cost_size(prec), as = acc_size(prec);
+        const int64_t maxlen = std::max(maxX, maxY);
+        const int64_t nflags = (maxlen + 63) / 64, zero_words = nflags + kTailWords;
+        const int64_t *offYh = sym ? offX : offY;
+        for (int64_t i = 0; i < nX; ++i) {
+            const int64_t li = offX[i + 1] - offX[i];
+            if (li <= kshort) continue;
+            for (int64_t j = sym ? i + 1 : 0; j < nY; ++j) {
+                const int64_t lj = offYh[j + 1] - offYh[j];
+                if (lj <= kshort) continue;
+                const char *ra = (const char *)L.rowsX + (size_t)(offX[i] + i) * S * cs;
+                const char *rb = (const char *)L.rowsY + (size_t)(offYh[j] + j) * S * cs;
+                // the longer series streams, the shorter spreads over the lanes
+                const bool swap = lj > li;
+                const int64_t nA = swap ? lj : li, nB = swap ? li : lj;
+                // zero flags and ticket (the staging kernel's zeroing pass)
+                e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, 0, 0, 0, L.rowsX,
+                                 (uint32_t *)L.flags, zero_words, st);
+                if (e != hipSuccess) return fail_hip(e, "flag reset launch");
+                uint32_t *flags = (uint32_t *)L.flags;
+                char *dst = (char *)Dk + (size_t)(i * nY + j) * as;
+                s = run_pair_sweep(prec, cp, prm, swap ? rb : ra, swap ? ra : rb, nA, nB, L.bnd, flags,
+                                   flags + nflags, nullptr, dst, nullptr, st);
+                if (s != TWED_OK) return s;
+                if (sym) {
+                    e = launch_copy_one(prec, dst, (char *)Dk + (size_t)(j * nY + i) * as, st);
+                    if (e != hipSuccess) return fail_hip(e, "mirror launch");
+                }
+            }
+        }
+    }
+    if (widen) {
+        e = launch_widen((const float *)Dk, (double *)D, nOut, st);
+        if (e != hipSuccess) return fail_hip(e, "widen launch");
+    }
+    return TWED_OK;
+}
+
+const char *twed_status_string(twed_status s)
+{
+    switch (s) {
+    case TWED_OK: return "ok";
+    case TWED_ERR_INVALID: return "invalid argument";
+    case TWED_ERR_UNSUPPORTED: return "unsupported argument";
+    case TWED_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case TWED_ERR_DEVICE: return "device error";
+    default: return "unknown status";
+    }
+}
+
+const char *twed_last_error(void) { return g_last_error.c_str(); }
+
+twed_status twed_stream_check(hipStream_t stream)
+{
+    g_last_error.clear();
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail_hip(e, "stream synchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "pending error");
+    return TWED_OK;
+}
+
+const char *twed_version(void) { return "libtwed 0.1 (gfx950)"; }
+
+}  // extern "C"

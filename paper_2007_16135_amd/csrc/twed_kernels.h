@@ -1,0 +1,95 @@
+// twed_kernels.h -- host-side launch interface of the TWED kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace twed {
+
+// Precision of one launch (resolved: no AUTO here).
+enum Prec : int { kF64 = 0, kF32 = 1, kF32Acc64 = 2 };
+
+// Sample dimensions the kernels are compiled for; a call with dim d runs the
+// smallest compiled DIMT >= d with the extra components zero.
+int dimt_for(int dim);
+// Elements per packed row for (precision, DIMT).
+int row_stride(Prec prec, int dimt);
+inline size_t cost_size(Prec p) { return p == kF64 ? 8 : 4; }
+inline size_t acc_size(Prec p) { return p == kF32 ? 4 : 8; }
+
+struct CostParams {
+    double nu, lambda, p;
+    int dim;   // real dimension
+    int dimt;  // compiled dimension
+    int pm;    // PMode
+};
+
+// Writes packed rows (zero pad row first) and deletion costs for nSeries
+// series.  `off` (device, nSeries+1 sample offsets) may be null for a single
+// series of n samples.  Row block of series s starts at row off[s] + s.
+// Also zeroes `zero_words` 32-bit words at `zero_ptr` (may be null).
+hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const void *T,
+                        const int64_t *off, int64_t nSeries, int64_t n_single, int64_t max_len,
+                        void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st);
+
+// Single pair, persistent wave pipeline over strips of 64*K columns.
+struct WavefrontArgs {
+    const void *rowsA, *rowsB;
+    int64_t nA, nB;
+    void *bnd;          // 2 * (nA+1) pairs (dp, x) of the accumulator type
+    uint32_t *flags;    // nStrips words, zero
+    uint32_t *ticket;   // two words, zero: ticket, then the wait-timeout error word
+    int64_t nStrips;
+    const void *beta;   // one cost element: FP32 cost offset (read in FP32 mode)
+    void *out;          // one accumulator element
+    void *dump;         // optional (nA+1)*(nB+1) accumulators
+    int grid;           // workgroups (one wave each)
+};
+hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, hipStream_t st);
+// FP32 pairs longer than this get a per-diagonal cost offset.
+constexpr int64_t kOffsetMinLength = 4096;
+// Writes the FP32 cost offset of one staged pair to beta (one cost element).
+hipError_t launch_offset(Prec prec, const CostParams &cp, const void *rowsA, int64_t nA, const void *rowsB,
+                         int64_t nB, void *beta, hipStream_t st);
+// Occupancy-derived worker count for one wavefront instantiation.
+int wavefront_max_workers(Prec prec, const CostParams &cp, int K);
+
+// Fills row 0 and column 0 of a dump matrix (0 at the corner, +inf elsewhere).
+hipError_t launch_dump_border(Prec prec, void *dump, int64_t nA, int64_t nB, hipStream_t st);
+
+// One launch per anti-diagonal over three diagonal vectors in device memory.
+struct DiagonalArgs {
+    const void *rowsA, *rowsB;
+    int64_t nA, nB;
+    void *z[3];         // three DP diagonals, nB+1 accumulators each
+    void *x[3];         // three X = DP + e diagonals
+    const void *beta;   // one cost element: FP32 cost offset (read in FP32 mode)
+    void *out;
+    void *dump;
+};
+hipError_t launch_diagonal(Prec prec, const CostParams &cp, const DiagonalArgs &a, hipStream_t st);
+
+// Batched pairs: one wave per pair, shorter series across the lanes.
+enum BatchMode : int { kSymmetric = 0, kRect = 1, kPairList = 2 };
+struct BatchArgs {
+    const void *rowsX, *rowsY;   // packed rows (with pad rows)
+    const int64_t *offX, *offY;  // device sample offsets (nX+1, nY+1)
+    const int32_t *order;        // symmetric: series order (longest first), nX entries
+    const int64_t *pairs;        // pair-list mode
+    int64_t nX, nY, nItems;
+    int mode;
+    void *D;
+    uint32_t *ticket;            // one word, zero
+    int grid;
+};
+hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hipStream_t st);
+int batch_kmax(int dimt);
+int batch_max_workers(Prec prec, const CostParams &cp);
+hipError_t launch_batch_diag_zero(Prec prec, void *D, int64_t n, hipStream_t st);
+// dst[0] = src[0] on the device (accumulator type of prec).
+hipError_t launch_copy_one(Prec prec, const void *src, void *dst, hipStream_t st);
+// dst[i] = (double)src[i] for n floats.
+hipError_t launch_widen(const float *src, double *dst, int64_t n, hipStream_t st);
+
+}  // namespace twed

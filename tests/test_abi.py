@@ -1,0 +1,152 @@
+"""The C ABI on the host: the library loads, exports every declared entry
+point, and rejects bad arguments before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2007_16135_amd as tw
+from paper_2007_16135_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "twed.h")
+
+INVALID, UNSUPPORTED, WORKSPACE = binding.TWED_ERR_INVALID, binding.TWED_ERR_UNSUPPORTED, binding.TWED_ERR_WORKSPACE
+
+
+@pytest.fixture(scope="module")
+def L():
+    return binding.load_library()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(twed_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "twed_pair" in names and "twed_batch" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in twed.h but not exported"
+    assert set(binding.EXPORTS) <= set(names)
+
+
+def test_params_struct_layout(L):
+    # the binding's struct must match the header's field order and size
+    prm = binding.TwedParams()
+    L.twed_params_default(ctypes.byref(prm))
+    assert ctypes.sizeof(prm) == 48
+    assert prm.nu == 0.001 and prm.lambda_ == 1.0 and prm.p == 1.0 and prm.dim == 1
+    assert prm.precision == 0 and prm.algo == 0 and prm.strip_k == 0
+
+
+def test_status_strings(L):
+    for s in range(5):
+        assert L.twed_status_string(s)
+    assert L.twed_version().startswith(b"libtwed")
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+
+
+def _pair(L, prm, nA=10, nB=10, A=FAKE, TA=FAKE, B=FAKE, TB=FAKE, out=FAKE, ws=None, wsb=0):
+    return L.twed_pair(A, TA, nA, B, TB, nB, ctypes.byref(prm) if prm is not None else None, out,
+                       ws, wsb, None)
+
+
+def test_pair_argument_errors(L):
+    good = tw.make_params()
+    assert _pair(L, None) == INVALID
+    assert _pair(L, good, nA=0) == INVALID
+    assert _pair(L, good, nB=-3) == INVALID
+    assert _pair(L, good, A=None) == INVALID
+    assert _pair(L, good, TB=None) == INVALID
+    assert _pair(L, good, out=None) == INVALID
+    for kw in [dict(nu=-1.0), dict(lam=-0.5), dict(p=0.5), dict(nu=float("nan")),
+               dict(lam=float("inf")), dict(p=float("inf")), dict(dim=0)]:
+        assert _pair(L, tw.make_params(**kw)) == INVALID, kw
+    assert _pair(L, tw.make_params(dim=17)) == UNSUPPORTED
+    assert _pair(L, tw.make_params(precision=7)) == INVALID
+    assert _pair(L, tw.make_params(algo=5)) == INVALID
+    assert _pair(L, tw.make_params(strip_k=3)) == INVALID
+    assert _pair(L, good, nA=1 << 31) == UNSUPPORTED
+    # valid arguments, no or short workspace
+    assert _pair(L, good) == WORKSPACE
+    need = L.twed_pair_workspace_size(10, 10, ctypes.byref(good))
+    assert need > 0
+    assert _pair(L, good, ws=FAKE, wsb=need - 1) == WORKSPACE
+    assert _pair(L, good, ws=ctypes.c_void_p(0x1001), wsb=need) == WORKSPACE  # misaligned
+    assert L.twed_last_error()
+
+
+def test_pair_matrix_needs_dp(L):
+    good = tw.make_params()
+    assert L.twed_pair_matrix(FAKE, FAKE, 4, FAKE, FAKE, 4, ctypes.byref(good), FAKE, None, None, 0,
+                              None) == INVALID
+
+
+def test_workspace_sizes(L):
+    for prec in ("f64", "f32", "f32_acc64"):
+        prm = tw.make_params(dim=3, precision=prec)
+        s1 = L.twed_pair_workspace_size(1000, 1000, ctypes.byref(prm))
+        s2 = L.twed_pair_workspace_size(100000, 100000, ctypes.byref(prm))
+        assert 0 < s1 < s2
+        # linear memory: O(nA + nB), not O(nA * nB)
+        assert s2 < 100 * s1 * 1.5
+    bad = tw.make_params(nu=-1)
+    assert L.twed_pair_workspace_size(10, 10, ctypes.byref(bad)) == 0
+    assert L.twed_pair_workspace_size(0, 10, ctypes.byref(tw.make_params())) == 0
+    # the wavefront state for n = 1e6 (8-D, FP32 costs, FP64 accumulators)
+    # stays within a few hundred MB
+    prm = tw.make_params(dim=8, p=2, precision="f32_acc64")
+    assert L.twed_pair_workspace_size(10**6, 10**6, ctypes.byref(prm)) < 200 * 2**20
+
+
+def _batch(L, prm, offX, nX=None, offY=None, nY=None, X=FAKE, TX=FAKE, Y=None, TY=None, pairs=None, nP=0,
+           D=FAKE, ws=None, wsb=0):
+    ox = np.ascontiguousarray(offX, dtype=np.int64) if offX is not None else None
+    oy = np.ascontiguousarray(offY, dtype=np.int64) if offY is not None else None
+    px = ox.ctypes.data_as(binding._i64p) if ox is not None else None
+    py = oy.ctypes.data_as(binding._i64p) if oy is not None else None
+    if nX is None:
+        nX = len(ox) - 1
+    if nY is None:
+        nY = nX if oy is None else len(oy) - 1
+    return L.twed_batch(X, TX, px, nX, Y, TY, py, nY, pairs, nP, ctypes.byref(prm), D, ws, wsb, None)
+
+
+def test_batch_argument_errors(L):
+    prm = tw.make_params(precision="f32")
+    assert _batch(L, prm, [0, 3, 5]) == WORKSPACE           # valid, no workspace
+    assert _batch(L, prm, [1, 3, 5]) == INVALID             # must start at 0
+    assert _batch(L, prm, [0, 3, 3]) == INVALID             # empty series
+    assert _batch(L, prm, [0, 3, 2]) == INVALID             # decreasing
+    assert _batch(L, prm, None, nX=2) == INVALID
+    assert _batch(L, prm, [0, 3, 5], X=None) == INVALID
+    assert _batch(L, prm, [0, 3, 5], D=None) == INVALID
+    assert _batch(L, prm, [0, 3, 5], nY=3) == INVALID       # symmetric needs nY == nX
+    assert _batch(L, prm, [0, 3, 5], nY=2, TY=FAKE) == INVALID
+    assert _batch(L, prm, [0, 3, 5], offY=[0, 2], nY=1, Y=FAKE, TY=None) == INVALID
+    assert _batch(L, prm, [0, 3, 5], offY=[0, 2], nY=1, Y=FAKE, TY=FAKE, pairs=FAKE, nP=-1) == INVALID
+    # pair list with both collections holding over-long series
+    longs = [0, 5000, 10000]
+    assert _batch(L, prm, longs, offY=longs, nY=2, Y=FAKE, TY=FAKE, pairs=FAKE, nP=1) == UNSUPPORTED
+    need = L.twed_batch_workspace_size(np.array([0, 3, 5], np.int64).ctypes.data_as(binding._i64p), 2,
+                                       None, 0, ctypes.byref(prm))
+    assert need > 0
+    assert _batch(L, prm, [0, 3, 5], ws=FAKE, wsb=need - 1) == WORKSPACE
+
+
+def test_batch_max_short_length(L):
+    assert L.twed_batch_max_short_length(1) == 1024
+    assert L.twed_batch_max_short_length(3) == 512
+    assert L.twed_batch_max_short_length(8) == 256
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.load_library(str(tmp_path / "nope.so"))

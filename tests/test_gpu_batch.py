@@ -1,0 +1,149 @@
+"""Batched TWED (one persistent launch over many pairs) against the CPU oracle.
+
+Bars as for single pairs: FP64 within 1e-12 relative, FP32 within 1e-5 of the
+FP64 oracle on the same rounded inputs; structural properties (symmetry, zero
+diagonal, equality with the single-pair call) exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_16135_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2007_16135_amd as tw  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(col, precision):
+    dt = torch.float64 if precision == "f64" else torch.float32
+    npdt = np.float64 if precision == "f64" else np.float32
+    X = torch.as_tensor(np.ascontiguousarray(col.X.astype(npdt)), device="cuda")
+    T = torch.as_tensor(np.ascontiguousarray(col.T.astype(npdt)), device="cuda")
+    assert X.dtype == dt
+    return X, T
+
+
+def ref_inputs(col, precision):
+    if precision == "f64":
+        return col.X, col.T
+    return col.X.astype(np.float32).astype(np.float64), col.T.astype(np.float32).astype(np.float64)
+
+
+def max_rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32_acc64": 1e-6}
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_acc64"])
+def test_symmetric_small(precision):
+    col = synth.batch_collection(40, 1, 300, seed=11)
+    X, T = to_dev(col, precision)
+    say(f"batch symmetric 40 {precision}")
+    D = tw.twed_batch(X, T, col.off, nu=1e-3, lam=1.0, p=1.0, precision=precision)
+    torch.cuda.synchronize()
+    D = D.cpu().numpy().astype(np.float64)
+    Xr, Tr = ref_inputs(col, precision)
+    ref = oracle.get().all_pairs(Xr, Tr, col.off, 1e-3, 1.0, 1.0)
+    assert np.array_equal(D, D.T)
+    assert np.all(np.diag(D) == 0)
+    assert max_rel(D, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1.0), (3, 2.0), (5, 3.0), (8, 2.0)])
+def test_symmetric_multidim(dim, p):
+    rng_cols = []
+    for k in range(24):
+        r = np.random.default_rng([77, k])
+        L = int(r.integers(1, 200))
+        rng_cols.append((synth.walk(r, L, dim), synth.irregular_times(r, L)))
+    col = synth.pack([x for x, _ in rng_cols], [t for _, t in rng_cols])
+    X, T = to_dev(col, "f64")
+    say(f"batch multidim dim{dim} p{p}")
+    D = tw.twed_batch(X, T, col.off, nu=0.05, lam=0.5, p=p, precision="f64")
+    torch.cuda.synchronize()
+    ref = oracle.get().all_pairs(col.X, col.T, col.off, 0.05, 0.5, p)
+    assert max_rel(D.cpu().numpy(), ref) <= 1e-12
+
+
+def test_rectangular_and_pair_list():
+    cx = synth.batch_collection(17, 1, 400, seed=21)
+    cy = synth.batch_collection(13, 1, 400, seed=22)
+    X, TX = to_dev(cx, "f64")
+    Y, TY = to_dev(cy, "f64")
+    say("batch rectangular 17x13")
+    D = tw.twed_batch(X, TX, cx.off, Y, TY, cy.off, nu=0.01, lam=0.3, p=1.0, precision="f64")
+    torch.cuda.synchronize()
+    prs = np.array([(i, j) for i in range(17) for j in range(13)], np.int64)
+    ref = oracle.get().pairs(cx.X, cx.T, cx.off, cy.X, cy.T, cy.off, prs, 0.01, 0.3, 1.0)
+    assert max_rel(D.cpu().numpy().reshape(-1), ref) <= 1e-12
+
+    rng = np.random.default_rng(3)
+    pl = np.stack([rng.integers(0, 17, 300), rng.integers(0, 13, 300)], axis=1).astype(np.int64)
+    say("batch pair list 300")
+    Dp = tw.twed_batch(X, TX, cx.off, Y, TY, cy.off, pairs=torch.as_tensor(pl, device="cuda"),
+                       nu=0.01, lam=0.3, p=1.0, precision="f64")
+    torch.cuda.synchronize()
+    Dm = D.cpu().numpy()
+    assert np.array_equal(Dp.cpu().numpy(), Dm[pl[:, 0], pl[:, 1]])
+
+
+def test_entries_equal_single_pair_call():
+    col = synth.batch_collection(12, 1, 700, seed=31)
+    X, T = to_dev(col, "f64")
+    D = tw.twed_batch(X, T, col.off, nu=1e-3, lam=1.0, p=1.0, precision="f64").cpu().numpy()
+    for (i, j) in [(0, 1), (3, 7), (11, 2), (5, 9)]:
+        a0, a1 = col.off[i], col.off[i + 1]
+        b0, b1 = col.off[j], col.off[j + 1]
+        say(f"pair call {i},{j}")
+        v = tw.twed_pair(X[a0:a1], T[a0:a1], X[b0:b1], T[b0:b1], 1e-3, 1.0, 1.0, "f64")
+        torch.cuda.synchronize()
+        assert float(v.item()) == D[i, j]
+
+
+def test_empty_pair_list_and_single_series():
+    col = synth.batch_collection(1, 5, 50, seed=41)
+    X, T = to_dev(col, "f32")
+    D = tw.twed_batch(X, T, col.off, precision="f32")
+    torch.cuda.synchronize()
+    assert D.shape == (1, 1) and float(D[0, 0]) == 0.0
+    Dp = tw.twed_batch(X, T, col.off, X, T, col.off, pairs=torch.zeros((0, 2), dtype=torch.int64, device="cuda"),
+                       precision="f32")
+    assert Dp.numel() == 0
+
+
+def test_all_pairs_2048_sampled():
+    """2,048 1-D FP32 walks, lengths U[64,1024], in the benchmark's launch
+    configuration; 1,500 sampled entries checked against the FP64 oracle."""
+    col = synth.batch_collection(2048, 64, 1024)
+    X, T = to_dev(col, "f32")
+    say("batch 2048 all pairs f32")
+    D = tw.twed_batch(X, T, col.off, nu=1e-3, lam=1.0, p=1.0, precision="f32")
+    torch.cuda.synchronize()
+    D = D.cpu().numpy()
+    assert np.array_equal(D, D.T) and np.all(np.diag(D) == 0)
+    rng = np.random.default_rng(5)
+    i = rng.integers(0, 2048, 1500)
+    j = rng.integers(0, 2048, 1500)
+    keep = i != j
+    prs = np.stack([i[keep], j[keep]], axis=1).astype(np.int64)
+    Xr, Tr = ref_inputs(col, "f32")
+    say("oracle on sampled entries")
+    ref = oracle.get().pairs(Xr, Tr, col.off, Xr, Tr, col.off, prs, 1e-3, 1.0, 1.0)
+    err = max_rel(D[prs[:, 0], prs[:, 1]], ref)
+    say(f"max relative error of sampled entries: {err:.3e}")
+    assert err <= 1e-5

@@ -1,0 +1,263 @@
+"""Single-pair parity: the HIP sweeps against the CPU oracle (GPU only).
+
+Bars (from the arithmetic): FP64 within 1e-12 relative of the oracle (the
+sweep re-associates the match cost as (DP + e_prev) + e_cur, and the oracle
+uses DP + ((d1 + d2) + nu*(t1 + t2))); integer-valued worked examples
+bitwise; FP32 within 1e-5 relative of the FP64 oracle run on the same
+FP32-rounded inputs; FP32 costs with FP64 accumulators within 1e-6.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle_pins as pins
+from paper_2007_16135_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2007_16135_amd as tw  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+RTOL = {"f64": 1e-12, "f32": 1e-5, "f32_acc64": 1e-6}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dt):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+
+
+def dtype_of(precision):
+    return torch.float64 if precision == "f64" else torch.float32
+
+
+class Unavailable(Exception):
+    pass
+
+
+def _call(fn, *a, **kw):
+    try:
+        return fn(*a, **kw)
+    except tw.TwedError as e:
+        if e.status == 2 and "switched off" in str(e):
+            raise Unavailable(str(e))
+        raise
+
+
+def gpu_twed(A, TA, B, TB, nu, lam, p, precision="f64", **kw):
+    dt = dtype_of(precision)
+    A = np.asarray(A, dtype=np.float64).reshape(len(TA), -1)
+    B = np.asarray(B, dtype=np.float64).reshape(len(TB), -1)
+    out = _call(tw.twed_pair, dev(A, dt), dev(TA, dt), dev(B, dt), dev(TB, dt), nu, lam, p, precision, **kw)
+    torch.cuda.synchronize()
+    return float(out.item())
+
+
+def gpu_matrix(A, TA, B, TB, nu, lam, p, precision="f64", **kw):
+    dt = dtype_of(precision)
+    A = np.asarray(A, dtype=np.float64).reshape(len(TA), -1)
+    B = np.asarray(B, dtype=np.float64).reshape(len(TB), -1)
+    out, dp = _call(tw.twed_pair_matrix, dev(A, dt), dev(TA, dt), dev(B, dt), dev(TB, dt), nu, lam, p,
+                    precision, **kw)
+    torch.cuda.synchronize()
+    return float(out.item()), dp.cpu().numpy().astype(np.float64)
+
+
+def _switched_off(cfg):
+    """True if the library refuses this sweep before any launch (argument-level
+    check with a deliberately missing workspace: no device work happens)."""
+    import ctypes
+    prm = tw.make_params(precision="f64", algo=cfg["algo"], strip_k=cfg.get("strip_k", 0))
+    L = tw.load_library()
+    fake = ctypes.c_void_p(256)
+    st = L.twed_pair(fake, fake, 1, fake, fake, 1, ctypes.byref(prm), fake, None, 0, None)
+    return st == 2 and b"switched off" in L.twed_last_error()
+
+
+def rounded(x, precision):
+    x = np.asarray(x, dtype=np.float64)
+    return x.astype(np.float32).astype(np.float64) if precision != "f64" else x
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+ALL_ALGOS = [dict(algo="wavefront", strip_k=k) for k in (1, 2, 4, 8)] + [dict(algo="diagonal")]
+ALGOS = [c for c in ALL_ALGOS if not _switched_off(c)]
+OFF = [c for c in ALL_ALGOS if c not in ALGOS]
+FAST = [c for c in ALGOS if c["algo"] != "diagonal"] or ALGOS  # sweep used for the long cases
+
+
+def test_report_switched_off_sweeps():
+    if OFF:
+        pytest.skip(f"switched off in this build: {OFF}")
+
+
+@pytest.mark.parametrize("cfg", ALL_ALGOS, ids=lambda c: f"{c['algo']}{c.get('strip_k', '')}")
+def test_worked_examples_bitwise(cfg):
+    if cfg in OFF:
+        pytest.skip("sweep switched off in this build")
+    for c in pins.load_worked_examples():
+        A = np.array(c["A"], float).reshape(-1, c["dim"])
+        B = np.array(c["B"], float).reshape(-1, c["dim"])
+        say(f"worked example {c['name']} {cfg}")
+        if c["exact"]:
+            v, dp = gpu_matrix(A, c["TA"], B, c["TB"], c["nu"], c["lambda"], c["p"], **cfg)
+            want = np.array([[np.inf if x == "inf" else x for x in row] for row in c["DP"]], float)
+            assert np.array_equal(dp, want), (dp, want)
+            assert v == c["twed"]
+        else:
+            v = gpu_twed(A, c["TA"], B, c["TB"], c["nu"], c["lambda"], c["p"], **cfg)
+            assert rel(v, c["twed"]) <= 1e-14
+
+
+SHAPES = [(1, 1), (1, 7), (7, 1), (2, 3), (5, 9), (9, 5), (63, 64), (64, 63), (65, 65), (1, 700),
+          (700, 1), (127, 129), (129, 127), (200, 513), (513, 200), (1023, 1025), (1025, 1023),
+          (3000, 40), (40, 3000)]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_acc64"])
+def test_random_shapes_vs_oracle(precision):
+    rng = np.random.default_rng(2024)
+    orc = oracle.get()
+    for k, (nA, nB) in enumerate(SHAPES):
+        dim = [1, 2, 3, 5, 8][k % 5]
+        p = [1.0, 2.0, 3.0][k % 3] if dim > 1 else 1.0
+        nu = [0.0, 1e-3, 0.5][k % 3]
+        lam = [0.0, 1.0, 5.0][(k // 3) % 3]
+        A, TA = pins.rand_series(rng, nA, dim)
+        B, TB = pins.rand_series(rng, nB, dim)
+        A, TA, B, TB = (rounded(x, precision) for x in (A, TA, B, TB))
+        want = orc.twed(A, TA, B, TB, nu, lam, p)
+        for cfg in ALGOS:
+            if cfg["algo"] == "diagonal" and nA + nB > 2000:
+                continue
+            say(f"shape {nA}x{nB} dim{dim} p{p} nu{nu} lam{lam} {precision} {cfg}")
+            got = gpu_twed(A, TA, B, TB, nu, lam, p, precision, **cfg)
+            tol = RTOL[precision] * (10 if p == 3.0 and precision != "f64" else 1)
+            assert rel(got, want) <= tol, (nA, nB, dim, p, cfg, got, want)
+
+
+def test_band_dump_matches_oracle_matrix():
+    """Every DP cell (row 0, column 0 and the interior), several strips wide."""
+    rng = np.random.default_rng(7)
+    orc = oracle.get()
+    for (nA, nB, dim, p) in [(10, 12, 1, 1.0), (64, 64, 2, 2.0), (33, 200, 3, 2.0), (150, 70, 2, 1.0),
+                             (5, 300, 1, 1.0)]:
+        A, TA = pins.rand_series(rng, nA, dim)
+        B, TB = pins.rand_series(rng, nB, dim)
+        _, want = orc.twed(A, TA, B, TB, 0.3, 0.7, p, matrix=True)
+        for cfg in [c for c in ALGOS if c.get("strip_k", 1) <= 2]:
+            say(f"dump {nA}x{nB} dim{dim} {cfg}")
+            _, got = gpu_matrix(A, TA, B, TB, 0.3, 0.7, p, **cfg)
+            assert np.array_equal(np.isinf(got), np.isinf(want))
+            fin = np.isfinite(want)
+            err = np.max(np.abs(got[fin] - want[fin]) / np.maximum(np.abs(want[fin]), 1e-300))
+            assert err <= 1e-12, err
+
+
+def test_schedule_invariance_bitwise():
+    """Strip width and algorithm change only the evaluation order across
+    cells, never a cell's own arithmetic: FP64 results agree to the bit."""
+    for n, prec in ((3000, "f64"), (3000, "f32"), (5000, "f32")):
+        c = synth.single_pair_3d(n)
+        vals = []
+        for cfg in ALGOS:
+            say(f"invariance n{n} {prec} {cfg}")
+            vals.append(gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec, **cfg))
+        assert len(set(vals)) == 1, (n, prec, vals)
+
+
+@pytest.mark.parametrize("nA,nB", [(2500, 1700), (6000, 4500)])
+def test_symmetry_bitwise(nA, nB):
+    """D(A,B) == D(B,A) to the bit; the second shape is long enough for the
+    FP32 cost offset, which is symmetric in (A, B) too."""
+    c = synth.random_pair(31, 32, nA, nB, 2, irregular=True, nu=0.05, lam=0.4, p=2.0)
+    for prec in ("f64", "f32", "f32_acc64"):
+        say(f"symmetry {nA}x{nB} {prec}")
+        ab = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec)
+        ba = gpu_twed(c.B, c.TB, c.A, c.TA, c.nu, c.lam, c.p, prec)
+        assert ab == ba
+
+
+def test_identity_is_zero():
+    c = synth.single_pair_3d(5000)
+    for prec in ("f64", "f32", "f32_acc64"):
+        say(f"identity {prec}")
+        assert gpu_twed(c.A, c.TA, c.A, c.TA, c.nu, c.lam, c.p, prec) == 0.0
+
+
+def _golden():
+    with open(os.path.join(GOLDEN, "oracle_values.json")) as f:
+        return {c["name"]: c for c in json.load(f)["cases"]}
+
+
+def test_walk1d_n1000():
+    g = _golden()
+    c = synth.single_pair_1d(1000)
+    for prec, key in (("f64", "walk1d_n1000"), ("f32", "walk1d_n1000_f32"), ("f32_acc64", "walk1d_n1000_f32")):
+        for cfg in ALGOS:
+            say(f"walk1d n1000 {prec} {cfg}")
+            got = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec, **cfg)
+            assert rel(got, g[key]["value"]) <= RTOL[prec], (prec, cfg, got)
+
+
+def test_walk3d_n100000_full():
+    """3-D walks, n = 100,000, irregular times: the full-size pair."""
+    g = _golden()
+    c = synth.single_pair_3d(100000)
+    say("walk3d n1e5 f64")
+    got = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f64")
+    assert rel(got, g["walk3d_n100000"]["value"]) <= 1e-12
+    want32 = g["walk3d_n100000_f32"]["value"]
+    say("walk3d n1e5 f32_acc64")
+    got = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f32_acc64")
+    assert rel(got, want32) <= 1e-6
+    say("walk3d n1e5 f32")
+    got32 = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f32")
+    say(f"walk3d n1e5 f32 relative error {rel(got32, want32):.3e}")
+    assert rel(got32, want32) <= 1e-5
+
+
+def test_walk3d_prefix():
+    g = _golden()
+    c = synth.single_pair_3d(100000).prefix(10000)
+    for prec, key in (("f64", "walk3d_n100000_prefix10000"), ("f32", "walk3d_n100000_prefix10000_f32"),
+                      ("f32_acc64", "walk3d_n100000_prefix10000_f32")):
+        say(f"walk3d prefix {prec}")
+        got = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec)
+        assert rel(got, g[key]["value"]) <= RTOL[prec]
+
+
+def test_walk8d_prefix():
+    g = _golden()
+    full = synth.single_pair_8d(1000000)
+    for n, key, prec in ((10000, "walk8d_n1000000_prefix10000_f32", "f32_acc64"),
+                         (10000, "walk8d_n1000000_prefix10000", "f64"),
+                         (20000, "walk8d_n1000000_prefix20000_f32", "f32_acc64")):
+        c = full.prefix(n)
+        say(f"walk8d prefix {n} {prec}")
+        got = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec)
+        assert rel(got, g[key]["value"]) <= RTOL[prec]
+
+
+def test_auto_precision_policy():
+    """AUTO: FP32 accumulators up to the threshold, FP64 beyond; f64 result."""
+    c = synth.single_pair_3d(4000).astype(np.float32)
+    f32 = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f32")
+    acc = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f32_acc64")
+    lo = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "auto", acc64_threshold=4000)
+    hi = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "auto", acc64_threshold=3999)
+    assert lo == f32 and hi == acc
