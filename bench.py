@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched all-pairs measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--cpu-n", type=int, default=30000, help="prefix length of the CPU oracle sample")
+    ap.add_argument("--calib-bytes", type=int, default=0,
+                    help="first run one device-to-device copy of this many bytes (counter calibration)")
     return ap.parse_args()
 
 
@@ -88,6 +90,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     tw.load_library()
+    if args.calib_bytes > 0:
+        # a plain copy of known size: rocprofv3's FETCH_SIZE / WRITE_SIZE for
+        # this dispatch calibrate the counters read for the sweep kernel
+        src = torch.ones(args.calib_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- headline: one 8-D pair, n = m = 1e6, FP32 costs + FP64 accumulators
     n = args.n

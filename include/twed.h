@@ -115,7 +115,9 @@ twed_status twed_pair(const void *A, const void *TA, int64_t nA,
 /* Same as twed_pair, and also writes every DP cell to `dp` (device,
  * (nA+1)*(nB+1) elements of the result type, row-major, row stride nB+1,
  * row 0 and column 0 included).  Meant for validation on small problems:
- * the caller owns `dp`; no size limit is imposed beyond memory. */
+ * the caller owns `dp`; no size limit is imposed beyond memory.  The
+ * wavefront sweep runs with strips of at most 2 columns per lane here
+ * (strip_k 3..8 gives TWED_ERR_UNSUPPORTED); TWED_AUTO is not accepted. */
 twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA,
                              const void *B, const void *TB, int64_t nB,
                              const twed_params *prm, void *out, void *dp,

@@ -31,12 +31,18 @@ __global__ __launch_bounds__(256) void stage_kernel(const CT *__restrict__ X, co
                                                     const int64_t *__restrict__ off, int64_t nSeries,
                                                     int64_t n_single, int dim, CostArgs<CT> ca,
                                                     CT *__restrict__ rows, uint32_t *zero_ptr,
-                                                    int64_t zero_words)
+                                                    int64_t zero_words, int64_t total_rows)
 {
     constexpr int S = Row<CT, DIMT>::kStride;
     const int64_t gtid = (int64_t)blockIdx.y * gridDim.x * blockDim.x + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t gsize = (int64_t)gridDim.x * gridDim.y * blockDim.x;
     for (int64_t w = gtid; w < zero_words; w += gsize) zero_ptr[w] = 0u;
+    // kRowPad zero rows before and after the packed rows (read, never used,
+    // by sweep lanes that run ahead of or behind the series)
+    for (int64_t w = gtid; w < (int64_t)kRowPad * S; w += gsize) {
+        rows[w - (int64_t)kRowPad * S] = CT(0);
+        rows[total_rows * S + w] = CT(0);
+    }
 
     for (int64_t s = blockIdx.y; s < nSeries; s += gridDim.y) {
         const int64_t b = off ? off[s] : 0;
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(256) void stage_kernel(const CT *__restrict__ X, co
 
 hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const void *T,
                         const int64_t *off, int64_t nSeries, int64_t n_single, int64_t max_len,
-                        void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st)
+                        int64_t total_rows, void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st)
 {
     // Deletion costs are a cost term: computed in the cost precision.
     const Prec cprec = prec == kF64 ? kF64 : kF32;
@@ -86,7 +92,7 @@ hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const vo
         if (gy < 1) gy = 1;
         hipLaunchKernelGGL((stage_kernel<CT, DIMT, PM>), dim3(gx, gy), dim3(256), 0, st,
                            (const CT *)X, (const CT *)T, off, nSeries, n_single, cp.dim,
-                           CostArgs<CT>::make(cp), (CT *)rows, zero_ptr, zero_words);
+                           CostArgs<CT>::make(cp), (CT *)rows, zero_ptr, zero_words, total_rows);
         return hipGetLastError();
     });
 }

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -50,6 +51,13 @@ struct Carver {
         return p;
     }
 };
+
+// Packed rows with kRowPad zero rows on each side; returns the row-0 pointer.
+void *take_rows(Carver &c, Prec prec, int dimt, int64_t rows)
+{
+    char *p = (char *)c.take(rows_bytes(prec, dimt, rows));
+    return p ? p + (size_t)kRowPad * (size_t)row_stride(prec, dimt) * cost_size(prec) : nullptr;
+}
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
@@ -142,8 +150,8 @@ PairLayout pair_layout(char *base, int64_t nA, int64_t nB, const twed_params *pr
     const size_t S = (size_t)row_stride(prec, dimt);
     Carver c{base};
     PairLayout L{};
-    L.rowsA = c.take((size_t)(nA + 1) * S * cs);
-    L.rowsB = c.take((size_t)(nB + 1) * S * cs);
+    L.rowsA = take_rows(c, prec, dimt, nA + 1);
+    L.rowsB = take_rows(c, prec, dimt, nB + 1);
     if (prm->algo == TWED_ALGO_DIAGONAL || (prm->algo == TWED_ALGO_AUTO && !wavefront_enabled())) {
         for (int i = 0; i < 3; ++i) L.z[i] = c.take((size_t)(nB + 1) * as);
         for (int i = 0; i < 3; ++i) L.x[i] = c.take((size_t)(nB + 1) * as);
@@ -203,7 +211,12 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     if (!wavefront_enabled())
         return fail(TWED_ERR_UNSUPPORTED, "the wavefront sweep is switched off in this build "
                                           "(an unexplained stall on its first device run is under investigation)");
-    const int K = choose_k(prm, nB);
+    int K = choose_k(prm, nB);
+    if (dump) {
+        // cell dumps exist for narrow strips only (a validation aid)
+        if (prm->strip_k > 2) return fail(TWED_ERR_UNSUPPORTED, "twed_pair_matrix takes strip_k 0, 1 or 2");
+        K = std::min(K, 2);
+    }
     WavefrontArgs w{};
     w.rowsA = rowsA;
     w.rowsB = rowsB;
@@ -216,6 +229,18 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     w.nStrips = (nB + 64 * K - 1) / (64 * K);
     w.out = out;
     w.dump = dump;
+    // Handoff granularity and read protocol; TWED_WAVEFRONT_SYNC="rows,mode"
+    // overrides them for tuning runs.
+    w.chunk_rows = 64;
+    w.sync_mode = 0;
+    if (const char *env = std::getenv("TWED_WAVEFRONT_SYNC")) {
+        int rows = 0, mode = -1;
+        if (std::sscanf(env, "%d,%d", &rows, &mode) == 2 && (rows == 16 || rows == 32 || rows == 64) &&
+            (mode == 0 || mode == 1)) {
+            w.chunk_rows = rows;
+            w.sync_mode = mode;
+        }
+    }
     int workers = wavefront_max_workers(prec, cp, K);
     if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
     w.grid = (int)std::min<int64_t>(w.nStrips, workers);
@@ -243,9 +268,9 @@ twed_status pair_impl(const void *A, const void *TA, int64_t nA, const void *B, 
     uint32_t *tail = flags + L.nflags;
     hipError_t e;
     // stage A (zeroing flags and ticket on the way), then B
-    e = launch_stage(prec, cp, A, TA, nullptr, 1, nA, nA, L.rowsA, flags, L.zero_words, st);
+    e = launch_stage(prec, cp, A, TA, nullptr, 1, nA, nA, nA + 1, L.rowsA, flags, L.zero_words, st);
     if (e != hipSuccess) return fail_hip(e, "staging launch");
-    e = launch_stage(prec, cp, B, TB, nullptr, 1, nB, nB, L.rowsB, nullptr, 0, st);
+    e = launch_stage(prec, cp, B, TB, nullptr, 1, nB, nB, nB + 1, L.rowsB, nullptr, 0, st);
     if (e != hipSuccess) return fail_hip(e, "staging launch");
     if (dp) {
         e = launch_dump_border(prec, dp, nA, nB, st);
@@ -295,8 +320,8 @@ BatchLayout batch_layout(char *base, int64_t totX, int64_t nX, int64_t maxX, int
     const size_t S = (size_t)row_stride(prec, dimt);
     Carver c{base};
     BatchLayout L{};
-    L.rowsX = c.take((size_t)(totX + nX) * S * cs);
-    L.rowsY = symmetric ? L.rowsX : c.take((size_t)(totY + nY) * S * cs);
+    L.rowsX = take_rows(c, prec, dimt, totX + nX);
+    L.rowsY = symmetric ? L.rowsX : take_rows(c, prec, dimt, totY + nY);
     L.offX = c.take((size_t)(nX + 1) * 8);
     L.offY = symmetric ? L.offX : c.take((size_t)(nY + 1) * 8);
     L.order = c.take((size_t)nX * 4);
@@ -437,10 +462,12 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
         e = hipMemcpyAsync(L.order, order.data(), (size_t)nX * 4, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return fail_hip(e, "order upload");
     }
-    e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, L.rowsX, (uint32_t *)L.zero, 1, st);
+    e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, totX + nX, L.rowsX,
+                     (uint32_t *)L.zero, 1, st);
     if (e != hipSuccess) return fail_hip(e, "staging launch");
     if (!sym) {
-        e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, L.rowsY, nullptr, 0, st);
+        e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, totY + nY, L.rowsY, nullptr, 0,
+                         st);
         if (e != hipSuccess) return fail_hip(e, "staging launch");
     }
     const bool widen = needs_widen(prm, prec);
@@ -491,7 +518,7 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
                 const bool swap = lj > li;
                 const int64_t nA = swap ? lj : li, nB = swap ? li : lj;
                 // zero flags and ticket (the staging kernel's zeroing pass)
-                e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, 0, 0, 0, L.rowsX,
+                e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, 0, 0, 0, totX + nX, L.rowsX,
                                  (uint32_t *)L.flags, zero_words, st);
                 if (e != hipSuccess) return fail_hip(e, "flag reset launch");
                 uint32_t *flags = (uint32_t *)L.flags;

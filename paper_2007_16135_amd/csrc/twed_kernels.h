@@ -25,13 +25,23 @@ struct CostParams {
     int pm;    // PMode
 };
 
+// Zero rows kept before and after every packed row buffer.
+constexpr int kRowPad = 64;
+// Bytes of a packed row buffer holding `rows` rows plus its padding.
+inline size_t rows_bytes(Prec prec, int dimt, int64_t rows)
+{
+    return (size_t)(rows + 2 * kRowPad) * (size_t)row_stride(prec, dimt) * cost_size(prec);
+}
+
 // Writes packed rows (zero pad row first) and deletion costs for nSeries
 // series.  `off` (device, nSeries+1 sample offsets) may be null for a single
 // series of n samples.  Row block of series s starts at row off[s] + s.
-// Also zeroes `zero_words` 32-bit words at `zero_ptr` (may be null).
+// `rows` points after the front padding of a buffer of total_rows rows
+// (rows_bytes); the padding rows are zeroed too.  Also zeroes `zero_words`
+// 32-bit words at `zero_ptr` (may be null).
 hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const void *T,
                         const int64_t *off, int64_t nSeries, int64_t n_single, int64_t max_len,
-                        void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st);
+                        int64_t total_rows, void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st);
 
 // Single pair, persistent wave pipeline over strips of 64*K columns.
 struct WavefrontArgs {
@@ -45,6 +55,8 @@ struct WavefrontArgs {
     void *out;          // one accumulator element
     void *dump;         // optional (nA+1)*(nB+1) accumulators
     int grid;           // workgroups (one wave each)
+    int chunk_rows;     // boundary rows per handoff: 16, 32 or 64
+    int sync_mode;      // SyncMode of wavefront.hip
 };
 hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, hipStream_t st);
 // FP32 pairs longer than this get a per-diagonal cost offset.

@@ -15,9 +15,10 @@
 //  * The left and up-left operands of a lane's first column come from lane
 //    l-1 through one DPP wave shift per step.
 //  * Lane 0 of strip s takes them from the right-boundary column of strip
-//    s-1 (DP and DP+e per row), which that strip's lane 63 writes to one of
-//    two global slots and publishes every 64 rows with a release flag; the
-//    consumer polls the flag and acquires before loading 64 rows at once.
+//    s-1 (DP and DP+e per row).  That strip collects its lane 63 outputs in
+//    a register (one DPP shift per step), writes them to one of two global
+//    slots every kChunk rows and publishes them with a release flag; the
+//    consumer polls the flag and acquires before loading kChunk rows at once.
 //    Two slots suffice: strip s+2 can only write row r after strip s+1 has
 //    published row r, which it does after reading it.
 //  * Waves take strips from an atomic ticket, so the wave that strip s waits
@@ -39,16 +40,87 @@ struct alignas(2 * sizeof(AT)) Pair2 {
     AT x;
 };
 
-template <typename CT, typename AT, int DIMT, int PM, int K>
+// Rows of the strip boundary handed over per flag update (a kernel argument,
+// 16, 32 or 64).
+
+// How a consumer reads a published boundary chunk.
+//   0 (default): agent-scope acquire fence, then ordinary loads -- the
+//      release/acquire pairing of the memory model.  The fence invalidates the
+//      local L2, which also drops cached rows of A for every wave on it.
+//   1: device-coherent (agent-scope atomic) loads of the chunk, issued after
+//      the flag load has returned, with only a workgroup-scope fence: the L2
+//      keeps its contents.  This leans on the hardware (no load is issued
+//      before the branch on the flag resolves) rather than on a formal
+//      acquire; measured no faster on MI355X, it is kept for tuning runs.
+enum SyncMode : int { kSyncAcquireFence = 0, kSyncCoherentLoads = 1 };
+
+template <typename AT>
+__device__ __forceinline__ Pair2<AT> load_coherent(const Pair2<AT> *p)
+{
+    if constexpr (sizeof(AT) == 8) {
+        const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+        const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return Pair2<AT>{__builtin_bit_cast(AT, a), __builtin_bit_cast(AT, b)};
+    } else {
+        const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+        const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return Pair2<AT>{__builtin_bit_cast(AT, (uint32_t)a), __builtin_bit_cast(AT, (uint32_t)(a >> 32))};
+    }
+}
+
+template <typename AT>
+__device__ __forceinline__ void store_coherent(Pair2<AT> *p, const Pair2<AT> &v)
+{
+    if constexpr (sizeof(AT) == 8) {
+        uint64_t *q = reinterpret_cast<uint64_t *>(p);
+        __hip_atomic_store(q, __builtin_bit_cast(uint64_t, v.dp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(q + 1, __builtin_bit_cast(uint64_t, v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        uint64_t *q = reinterpret_cast<uint64_t *>(p);
+        const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, v.dp) |
+                           ((uint64_t)__builtin_bit_cast(uint32_t, v.x) << 32);
+        __hip_atomic_store(q, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+// DPP control "wave_shl:1": lane i receives lane i+1; lane 63 keeps `old`.
+constexpr int kDppWaveShl1 = 0x130;
+
+__device__ __forceinline__ float collect(float v_lane63, float col)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, v_lane63), __builtin_bit_cast(int, col), kDppWaveShl1, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ double collect(double v_lane63, double col)
+{
+    uint64_t u = __builtin_bit_cast(uint64_t, col);
+    uint64_t o = __builtin_bit_cast(uint64_t, v_lane63);
+    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u,
+                                                        kDppWaveShl1, 0xf, 0xf, false);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
+                                                        kDppWaveShl1, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// rowsA points at row 0 of A and must stay readable from row -64 to row
+// nA + 64 (the staging pads the buffer): lanes that have not started yet, or
+// have finished, read rows outside 1..nA and compute values nobody uses, so
+// the row address needs no clamp.
+template <typename CT, typename AT, int DIMT, int PM, int K, bool DUMP>
 __global__ __launch_bounds__(64) void wavefront_kernel(const CT *__restrict__ rowsA, const CT *__restrict__ rowsB,
                                                        int nA, int nB, CostArgs<CT> ca, Pair2<AT> *bnd,
                                                        uint32_t *flags, uint32_t *ticket, uint32_t *err,
-                                                       int nStrips, const CT *beta_ptr, AT *out, AT *dump)
+                                                       int nStrips, const CT *beta_ptr, AT *out, AT *dump,
+                                                       int chunk_rows, int sync_mode)
 {
+    constexpr int S = Row<CT, DIMT>::kStride;
+    const int kChunk = chunk_rows;
     const int lane = threadIdx.x;
     constexpr int W = kWave * K;
     const AT INF = pinf<AT>();
     const CT beta = kShifted<AT> ? beta_ptr[0] : CT(0);
+    const CT *rowsA_lane = rowsA - (ptrdiff_t)lane * S;  // row t of this pointer = row t - lane of A
 
     for (;;) {
         const int s = (int)next_ticket(ticket);
@@ -93,13 +165,17 @@ __global__ __launch_bounds__(64) void wavefront_kernel(const CT *__restrict__ ro
         AT sh_xo = INF;
 
         const int T = nA + kWave;  // lane 63 reaches row nA at step nA + 63
-        Row<CT, DIMT> cur;
-        load_row<CT, DIMT>(rowsA, 0, cur);
+        Row<CT, DIMT> cur, nxt;
+        load_row<CT, DIMT>(rowsA_lane, 0, cur);
         Pair2<AT> chunk{INF, INF};
+        // Right-boundary collector: lane 63's (DP, X) of each step enters at
+        // lane 63 and moves down one lane per step.
+        AT col_dp = INF, col_x = INF;
 
-        for (int t0 = 0; t0 < T; t0 += kWave) {
+        for (int t0 = 0; t0 < T; t0 += kChunk) {
             if (has_in) {
-                const uint32_t need = (uint32_t)(t0 + kWave < nA ? t0 + kWave : nA);
+                // rows t0+1 .. t0+kChunk of the left boundary
+                const uint32_t need = (uint32_t)(t0 + kChunk < nA ? t0 + kChunk : nA);
                 // Bounded wait, uniform across the wave: a wave that gives up
                 // marks the error word (the result strip then reports NaN) and
                 // carries on, so every wave still reaches the end of the grid.
@@ -111,30 +187,38 @@ __global__ __launch_bounds__(64) void wavefront_kernel(const CT *__restrict__ ro
                         break;
                     }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 const int rr = t0 + 1 + lane < nA ? t0 + 1 + lane : nA;
-                chunk = in_slot[rr];
+                if (sync_mode == kSyncCoherentLoads) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    chunk = load_coherent(in_slot + rr);
+                } else {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    chunk = in_slot[rr];
+                }
             }
-            const int steps = T - t0 < kWave ? T - t0 : kWave;
-            for (int i = 0; i < steps; ++i) {
+            const int steps = T - t0 < kChunk ? T - t0 : kChunk;
+            // One step: sweep row t - lane with `use`, prefetch row t + 1 -
+            // lane into `fill`.  Steps alternate the two row buffers, so the
+            // prefetched row never has to be copied.
+            auto step = [&](int i, Row<CT, DIMT> &use, Row<CT, DIMT> &fill) {
                 const int t = t0 + i;
-                const int r = t - lane;
-                int rn = r + 1;
-                rn = rn < 0 ? 0 : (rn > nA ? nA : rn);
-                Row<CT, DIMT> nxt;
-                load_row<CT, DIMT>(rowsA, rn, nxt);
+                load_row<CT, DIMT>(rowsA_lane, t + 1, fill);
 
                 AT left = sh_l, xl;
-                lane_row<CT, AT, DIMT, PM, K>(L, cur, left, sh_xo, xl, ca.nu, ca.p, ca.invp, beta);
+                lane_row<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p, ca.invp, beta);
 
-                if (dump != nullptr && r >= 1 && r <= nA) {
+                if constexpr (DUMP) {
+                    const int r = t - lane;
+                    if (r >= 1 && r <= nA) {
 #pragma unroll
-                    for (int j = 0; j < K; ++j)
-                        if (c0 + j <= nB)
-                            dump[(size_t)r * (size_t)(nB + 1) + (size_t)(c0 + j)] =
-                                kShifted<AT> ? (AT)((double)L.up[j] + (double)beta * (double)(r + c0 + j)) : L.up[j];
+                        for (int j = 0; j < K; ++j)
+                            if (c0 + j <= nB)
+                                dump[(size_t)r * (size_t)(nB + 1) + (size_t)(c0 + j)] =
+                                    kShifted<AT> ? (AT)((double)L.up[j] + (double)beta * (double)(r + c0 + j))
+                                                 : L.up[j];
+                    }
                 }
-                // Stores of wave-uniform values are done by every lane (one
+                // The result is wave-uniform; every lane stores it (one
                 // transaction): no lane-conditional branch in the step loop.
                 if (result_strip && t == nA + lstar) {
                     AT res = L.up[0];
@@ -146,22 +230,41 @@ __global__ __launch_bounds__(64) void wavefront_kernel(const CT *__restrict__ ro
                     if (load_progress(err) != 0u) res = __builtin_nan("");
                     out[0] = res;
                 }
-                if (has_out && t >= kWave && t <= nA + kWave - 1)
-                    out_slot[t - (kWave - 1)] = Pair2<AT>{lane_value(left, kWave - 1), lane_value(xl, kWave - 1)};
 
                 const AT bl = has_in ? lane_value(chunk.dp, i) : INF;
                 const AT bx = has_in ? lane_value(chunk.x, i) : INF;
                 sh_xo = sh_x;
                 sh_l = shift_in(left, bl);
                 sh_x = shift_in(xl, bx);
-                cur = nxt;
-
                 if (has_out) {
-                    const int r63 = t - (kWave - 1);
-                    if (r63 >= 1 && ((r63 & (kWave - 1)) == 0 || r63 == nA)) {
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                        __hip_atomic_store(out_flag, (uint32_t)r63, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
+                    col_dp = collect(left, col_dp);
+                    col_x = collect(xl, col_x);
+                }
+            };
+            int i = 0;
+            for (; i + 1 < steps; i += 2) {
+                step(i, cur, nxt);
+                step(i + 1, nxt, cur);
+            }
+            if (i < steps) {
+                step(i, cur, nxt);
+                cur = nxt;
+            }
+            if (has_out) {
+                // lane kWave - steps + i holds row t0 + i - 63 of the boundary
+                // (lanes without a row of this chunk write slot row 0, which
+                // no consumer reads: no lane-conditional branch)
+                int r = t0 + lane - (kWave - steps) - (kWave - 1);
+                r = (lane >= kWave - steps && r >= 1 && r <= nA) ? r : 0;
+                if (sync_mode == kSyncCoherentLoads)
+                    store_coherent(out_slot + r, Pair2<AT>{col_dp, col_x});
+                else
+                    out_slot[r] = Pair2<AT>{col_dp, col_x};
+                const int last = t0 + steps - kWave;  // last boundary row of this chunk
+                if (last >= 1) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __hip_atomic_store(out_flag, (uint32_t)(last < nA ? last : nA), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
@@ -171,10 +274,23 @@ __global__ __launch_bounds__(64) void wavefront_kernel(const CT *__restrict__ ro
 template <typename CT, typename AT, int DIMT, int PM, int K>
 static hipError_t launch_k(const WavefrontArgs &a, const CostParams &cp, hipStream_t st)
 {
-    hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K>), dim3(a.grid), dim3(kWave), 0, st,
+    if (a.dump) {
+        // cell dumps are a validation aid: narrow strips only
+        if constexpr (K <= 2) {
+            hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, true>), dim3(a.grid), dim3(kWave), 0, st,
+                               (const CT *)a.rowsA, (const CT *)a.rowsB, (int)a.nA, (int)a.nB,
+                               CostArgs<CT>::make(cp), (Pair2<AT> *)a.bnd, a.flags, a.ticket, a.ticket + 1,
+                               (int)a.nStrips, (const CT *)a.beta, (AT *)a.out, (AT *)a.dump, a.chunk_rows,
+                               a.sync_mode);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, false>), dim3(a.grid), dim3(kWave), 0, st,
                        (const CT *)a.rowsA, (const CT *)a.rowsB, (int)a.nA, (int)a.nB, CostArgs<CT>::make(cp),
                        (Pair2<AT> *)a.bnd, a.flags, a.ticket, a.ticket + 1, (int)a.nStrips, (const CT *)a.beta,
-                       (AT *)a.out, (AT *)a.dump);
+                       (AT *)a.out, nullptr, a.chunk_rows, a.sync_mode);
     return hipGetLastError();
 }
 
@@ -182,8 +298,8 @@ template <typename CT, typename AT, int DIMT, int PM, int K>
 static int occupancy_k()
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wavefront_kernel<CT, AT, DIMT, PM, K>, kWave, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wavefront_kernel<CT, AT, DIMT, PM, K, false>, kWave,
+                                                     0) != hipSuccess)
         return 0;
     return blocks;
 }
