@@ -44,6 +44,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def counter_traffic(n, strip_k):
+    """HBM-side bytes per launch of the headline sweep from the committed
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy of known size),
+    or None when the sweep's sources changed since the counters were taken or
+    the workload differs from the one profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "wavefront_8d_n1e6_hbm_counters.md")
+    if n != 1_000_000 or strip_k not in (0, 8) or not os.path.exists(path):
+        return None
+    traffic, ok = None, True
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            traffic = float(line.split(":", 1)[1])
+        elif line.startswith("source_sha256 "):
+            name, digest = line[len("source_sha256 "):].split(":", 1)
+            src = os.path.join(ROOT, "paper_2007_16135_amd", "csrc", name.strip())
+            ok &= os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == digest.strip()
+    return traffic if ok else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,7 +161,8 @@ def main():
                    "cells_per_step": cells, "result": value},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
                      "unit": "T VALU lane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": None, "kernel": "wavefront_kernel<float,double,8,L2,K>",
+                     "traffic": counter_traffic(n, args.strip_k),
+                     "kernel": "wavefront_kernel<float,double,8,L2,K>",
                      "ops_per_cell": OPS_PER_CELL_8D_L2_ACC64, "kernel_avg_s": kern_s},
     }
 
