@@ -76,6 +76,12 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=30000, help="prefix length of the CPU oracle sample")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (counter calibration)")
+    ap.add_argument("--no-knn", action="store_true", help="skip the learned k-NN measurement")
+    ap.add_argument("--knn-db", type=int, default=100_000, help="k-NN database size")
+    ap.add_argument("--knn-queries", type=int, default=10_000, help="k-NN queries timed")
+    ap.add_argument("--knn-truth", type=int, default=1000,
+                    help="queries given exhaustive ground truth (recall sample)")
+    ap.add_argument("--knn-train-steps", type=int, default=500, help="training steps (2,048 pairs each)")
     return ap.parse_args()
 
 
@@ -94,6 +100,91 @@ def time_steps(fn, steps, warmup, torch):
     wall = time.perf_counter() - t0
     per = [a.elapsed_time(b) / 1e3 for a, b in ev]
     return wall, per
+
+
+def knn_bench(args, torch, tw, synth, dev, time_steps):
+    from paper_2007_16135_amd import knn
+    from paper_2007_16135_amd import binding as B
+    nu, lam, k = 1e-3, 1.0, 10
+    log(f"knn: generating database {args.knn_db} and {args.knn_queries} queries")
+    db = synth.knn_collection(args.knn_db, 3)
+    qs = synth.knn_collection(args.knn_queries, 4)
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a.reshape(-1), dtype=np.float32), device=dev)
+    DB, TDB, Q, TQ = f32(db.X), f32(db.T), f32(qs.X), f32(qs.T)
+    dbc = knn.Collection(DB, TDB, db.off)
+
+    tr = knn.Trainer(dbc, nu, lam, seed=0, batch_series=256, pairs_per_step=2048, refresh=100)
+    train_s = tr.train(args.knn_train_steps, log_every=100, log=log)
+    params = tr.params.clone()
+    t0 = time.perf_counter()
+    index = B.KnnIndex(DB, TDB, db.off, params, nu, lam)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log(f"knn: trained {tr.pairs_seen} pairs in {train_s:.1f} s, index built in {build_s:.2f} s")
+
+    # exhaustive ground truth on a sample of queries: FP32 TWED to every database series
+    nt = min(args.knn_truth, args.knn_queries)
+    qoff_t = qs.off[:nt + 1]
+    Qt, TQt = Q[:qoff_t[-1]], TQ[:qoff_t[-1]]
+    D = torch.empty((nt, args.knn_db), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(B.twed_batch_workspace_size(qoff_t, db.off, B.make_params(nu, lam, 1.0, 1, "f32")), 256),
+                     dtype=torch.uint8, device=dev)
+    exh_wall, _ = time_steps(lambda: B.twed_batch(Qt, TQt, qoff_t, DB, TDB, db.off, nu=nu, lam=lam, p=1.0,
+                                                   precision="f32", D=D, workspace=ws), 1, 0, torch)
+    Dn = D.cpu().numpy()
+    del D, ws
+    truth = np.argsort(Dn, axis=1, kind="stable")[:, :k]
+    exh_qps = nt / exh_wall
+    log(f"knn: exhaustive TWED for {nt} queries in {exh_wall:.2f} s ({exh_qps:.1f} q/s)")
+
+    def recall(n_cand, net=params):
+        ix = index if net is params else B.KnnIndex(DB, TDB, db.off, net, nu, lam)
+        ids, _ = ix.query(Qt, TQt, qoff_t, k=k, n_cand=n_cand)
+        r = knn.recall_at(ids.cpu().numpy(), truth)
+        if ix is not index:
+            ix.close()
+        return r
+
+    curve = {}
+    chosen = None
+    for c in (200, 400, 800, 1600, 3200, 6400, 12800, 25600, 51200):
+        c = min(c, args.knn_db)
+        curve[c] = recall(c)
+        log(f"knn: recall@10 with {c} candidates: {curve[c]:.4f}")
+        if curve[c] >= 0.99 and chosen is None:
+            chosen = c
+            break
+        if c == args.knn_db:
+            break
+    ablation = {"untrained_at_200": recall(200, torch.as_tensor(knn.init_params(0), device=dev)),
+                "network_only": recall(k)}
+    log(f"knn: ablations {ablation}")
+
+    def qps(n_cand):
+        ids = torch.empty((args.knn_queries, k), dtype=torch.int64, device=dev)
+        dist = torch.empty((args.knn_queries, k), dtype=torch.float32, device=dev)
+        wsq = torch.empty(max(index.workspace_size(qs.off, k, n_cand), 256), dtype=torch.uint8, device=dev)
+        wall, _ = time_steps(lambda: index.query(Q, TQ, qs.off, k=k, n_cand=n_cand, ids=ids, dist=dist,
+                                                 workspace=wsq), 2, 1, torch)
+        return args.knn_queries * 2 / wall
+
+    q200 = qps(200)
+    out = {"workload": f"{args.knn_db} database / {args.knn_queries} query 1-D FP32 series, lengths U[128,512], "
+                       f"half random walks, half noisy sinusoids of 8 classes; nu=1e-3, lambda=1, L1; k=10",
+           "train_pairs": tr.pairs_seen, "train_s": round(train_s, 2), "index_build_s": round(build_s, 3),
+           "recall_sample_queries": nt, "recall_curve": {str(c): round(r, 4) for c, r in curve.items()},
+           "recall@10_at_200": round(curve[200], 4), "queries_per_s_at_200": round(q200, 1),
+           "exhaustive_queries_per_s": round(exh_qps, 1), "ablation_recall@10": {
+               a: round(v, 4) for a, v in ablation.items()}}
+    if chosen is not None:
+        qc = q200 if chosen == 200 else qps(chosen)
+        out.update({"n_cand_for_recall_0.99": chosen, "recall@10": round(curve[chosen], 4),
+                    "queries_per_s": round(qc, 1), "speedup_vs_exhaustive": round(qc / exh_qps, 1)})
+    else:
+        out.update({"n_cand_for_recall_0.99": None, "recall@10": None, "queries_per_s": None})
+    index.close()
+    log(f"knn: {out}")
+    return out
 
 
 def main():
@@ -192,6 +283,10 @@ def main():
             "roofline_frac": round(OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / VALU_PEAK_TOPS, 4),
         }
         log(f"batch: {result['batched_all_pairs']}")
+
+    # ---- learned k-NN: train, index, query; recall against exhaustive TWED
+    if not args.no_knn:
+        result["knn"] = knn_bench(args, torch, tw, synth, dev, time_steps)
 
     # ---- CPU oracle on a bounded sample (prefix of the headline pair)
     if not args.no_cpu:

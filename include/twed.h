@@ -135,7 +135,8 @@ twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA,
  * pairs == NULL: D is the nX x nY matrix, row-major, D[i*nY + j] =
  *   TWED(X_i, Y_j).
  * pairs != NULL: device array of nPairs (i, j) int64 pairs (0 <= i < nX,
- *   0 <= j < nY); D[k] = TWED(X_{pairs[2k]}, Y_{pairs[2k+1]}).
+ *   0 <= j < nY); D[k] = TWED(X_{pairs[2k]}, Y_{pairs[2k+1]}).  A pair
+ *   outside those ranges cannot be checked on the host; its D[k] is NaN.
  * D: device, element type as `out` of twed_pair.  Every entry is
  * bitwise equal to what twed_pair returns for the same two series
  * and parameters, whichever operand is longer.

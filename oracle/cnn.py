@@ -174,3 +174,18 @@ def unflatten(vec):
 
 def n_params():
     return sum(KSIZE * CHANNELS[l] * CHANNELS[l + 1] + CHANNELS[l + 1] for l in range(4))
+
+
+def adamw_step(w, m, v, g, step, lr, weight_decay, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One AdamW update (Adam with decoupled weight decay, Loshchilov and
+    Hutter), FP64: moments m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2, bias
+    corrections 1 - b^step, then w <- w - lr (m_hat / (sqrt(v_hat) + eps) + wd w).
+    Returns new (w, m, v)."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    w = w - lr * (m_hat / (np.sqrt(v_hat) + eps) + weight_decay * w)
+    return w, m, v

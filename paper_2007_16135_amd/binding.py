@@ -23,7 +23,12 @@ EXPORTS = [
     "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_matrix",
     "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
+    "twed_embed_param_count", "twed_embed_max_length", "twed_embed_workspace_size", "twed_embed_forward",
+    "twed_embed_loss_grad", "twed_embed_adamw", "twed_knn_index_storage_size", "twed_knn_index_create",
+    "twed_knn_index_build_workspace_size", "twed_knn_index_build", "twed_knn_workspace_size", "twed_knn",
+    "twed_knn_index_destroy",
 ]
+EMBED_DIM = 128
 
 
 class TwedParams(ctypes.Structure):
@@ -77,6 +82,34 @@ def load_library(path: str = LIB_PATH):
     L.twed_stream_check.restype = ctypes.c_int
     L.twed_version.argtypes = []
     L.twed_version.restype = ctypes.c_char_p
+    # embedding network and k-NN index (include/twed_knn.h)
+    _sz = ctypes.c_size_t
+    L.twed_embed_param_count.argtypes = []
+    L.twed_embed_param_count.restype = _i64
+    L.twed_embed_max_length.argtypes = []
+    L.twed_embed_max_length.restype = _i64
+    L.twed_embed_workspace_size.argtypes = [_i64p, _i64, _i64]
+    L.twed_embed_workspace_size.restype = _sz
+    L.twed_embed_forward.argtypes = [_vp, _vp, _i64p, _i64, _vp, _vp, _sz, _vp]
+    L.twed_embed_forward.restype = ctypes.c_int
+    L.twed_embed_loss_grad.argtypes = [_vp, _vp, _i64p, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.twed_embed_loss_grad.restype = ctypes.c_int
+    L.twed_embed_adamw.argtypes = [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, _vp]
+    L.twed_embed_adamw.restype = ctypes.c_int
+    L.twed_knn_index_storage_size.argtypes = [_i64p, _i64, _pp]
+    L.twed_knn_index_storage_size.restype = _sz
+    L.twed_knn_index_create.argtypes = [_vp, _vp, _i64p, _i64, _vp, _pp, _vp, _sz, ctypes.POINTER(_vp)]
+    L.twed_knn_index_create.restype = ctypes.c_int
+    L.twed_knn_index_build_workspace_size.argtypes = [_vp]
+    L.twed_knn_index_build_workspace_size.restype = _sz
+    L.twed_knn_index_build.argtypes = [_vp, _vp, _sz, _vp]
+    L.twed_knn_index_build.restype = ctypes.c_int
+    L.twed_knn_workspace_size.argtypes = [_vp, _i64p, _i64, ctypes.c_int32, ctypes.c_int32]
+    L.twed_knn_workspace_size.restype = _sz
+    L.twed_knn.argtypes = [_vp, _vp, _vp, _i64p, _i64, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _sz, _vp]
+    L.twed_knn.restype = ctypes.c_int
+    L.twed_knn_index_destroy.argtypes = [_vp]
+    L.twed_knn_index_destroy.restype = None
     if path == LIB_PATH:
         _lib = L
     return L
@@ -269,3 +302,115 @@ def twed_host(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", device="cu
     out = twed_pair(t(A.reshape(len(A), -1)), t(TA), t(B.reshape(len(B), -1)), t(TB), nu, lam, p,
                     precision, **kw)
     return float(out.item())
+
+
+# ---- embedding network and learned k-NN (include/twed_knn.h) -----------------------
+
+def twed_embed_param_count() -> int:
+    return int(load_library().twed_embed_param_count())
+
+
+def twed_embed_max_length() -> int:
+    return int(load_library().twed_embed_max_length())
+
+
+def twed_embed_forward(params, X, off, emb=None, workspace=None, stream=None):
+    """Embeddings (nSeries, 128) float32 of packed 1-D series X (float32
+    device values) with host offsets `off`; params: the flat float32 vector."""
+    torch = _torch()
+    _dev(params, torch.float32, "params"); _dev(X, torch.float32, "X")
+    off, po = _offsets(off)
+    n = len(off) - 1
+    L = load_library()
+    ws = _workspace(L.twed_embed_workspace_size(po, n, 0), X.device, workspace)
+    if emb is None:
+        emb = torch.empty((n, EMBED_DIM), dtype=torch.float32, device=X.device)
+    _check(L.twed_embed_forward(params.data_ptr(), X.data_ptr(), po, n, emb.data_ptr(), ws.data_ptr(),
+                                ws.numel(), _stream(stream)))
+    return emb
+
+
+def twed_embed_loss_grad(params, X, off, pairs, target, grad=None, loss=None, emb=None, workspace=None,
+                         stream=None):
+    """Mean pair loss and its gradient.  pairs: int32 device (P, 2) indices
+    into the collection; target: float32 device (P,) TWED values.  Returns
+    (loss (1,), grad (param_count,), emb or None)."""
+    torch = _torch()
+    _dev(params, torch.float32, "params"); _dev(X, torch.float32, "X")
+    _dev(pairs, torch.int32, "pairs"); _dev(target, torch.float32, "target")
+    off, po = _offsets(off)
+    n = len(off) - 1
+    P = int(pairs.shape[0])
+    L = load_library()
+    ws = _workspace(L.twed_embed_workspace_size(po, n, P), X.device, workspace)
+    if grad is None:
+        grad = torch.empty(twed_embed_param_count(), dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(L.twed_embed_loss_grad(params.data_ptr(), X.data_ptr(), po, n, pairs.data_ptr(), target.data_ptr(),
+                                  P, loss.data_ptr(), grad.data_ptr(), emb.data_ptr() if emb is not None else None,
+                                  ws.data_ptr(), ws.numel(), _stream(stream)))
+    return loss, grad, emb
+
+
+def twed_embed_adamw(params, m, v, grad, step, lr, weight_decay=0.0, stream=None):
+    _check(load_library().twed_embed_adamw(params.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(),
+                                           int(step), float(lr), float(weight_decay), _stream(stream)))
+
+
+class KnnIndex:
+    """Learned k-NN index over packed 1-D FP32 series (twed_knn_index_*).
+    Keeps references to DB, TDB and params (the C index does not copy them)."""
+
+    def __init__(self, DB, TDB, offDB, params, nu=1e-3, lam=1.0, stream=None):
+        torch = _torch()
+        _dev(DB, torch.float32, "DB"); _dev(TDB, torch.float32, "TDB"); _dev(params, torch.float32, "params")
+        self.DB, self.TDB, self.params = DB, TDB, params
+        self.off, po = _offsets(offDB)
+        self.nDB = len(self.off) - 1
+        self.prm = make_params(nu, lam, 1.0, 1, "f32")
+        L = load_library()
+        need = L.twed_knn_index_storage_size(po, self.nDB, ctypes.byref(self.prm))
+        if need == 0:
+            _check(TWED_ERR_INVALID if L.twed_last_error() == b"" else TWED_ERR_UNSUPPORTED)
+        self.storage = _workspace(need, DB.device)
+        self._h = ctypes.c_void_p()
+        _check(L.twed_knn_index_create(DB.data_ptr(), TDB.data_ptr(), po, self.nDB, params.data_ptr(),
+                                       ctypes.byref(self.prm), self.storage.data_ptr(), self.storage.numel(),
+                                       ctypes.byref(self._h)))
+        # scratch returned to torch's caching allocator right away: later work
+        # that reuses it is ordered after the build on the same stream
+        ws = _workspace(L.twed_knn_index_build_workspace_size(self._h), DB.device)
+        _check(L.twed_knn_index_build(self._h, ws.data_ptr(), ws.numel(), _stream(stream)))
+
+    def workspace_size(self, offQ, k, n_cand) -> int:
+        offQ, pq = _offsets(offQ)
+        return int(load_library().twed_knn_workspace_size(self._h, pq, len(offQ) - 1, int(k), int(n_cand)))
+
+    def query(self, Q, TQ, offQ, k=10, n_cand=200, ids=None, dist=None, workspace=None, stream=None):
+        """(ids int64 (nQ, k), dist float32 (nQ, k)) of the k nearest series."""
+        torch = _torch()
+        _dev(Q, torch.float32, "Q"); _dev(TQ, torch.float32, "TQ")
+        offQ, pq = _offsets(offQ)
+        nQ = len(offQ) - 1
+        L = load_library()
+        ws = _workspace(L.twed_knn_workspace_size(self._h, pq, nQ, int(k), int(n_cand)), Q.device, workspace)
+        if ids is None:
+            ids = torch.empty((nQ, k), dtype=torch.int64, device=Q.device)
+        if dist is None:
+            dist = torch.empty((nQ, k), dtype=torch.float32, device=Q.device)
+        _check(L.twed_knn(self._h, Q.data_ptr(), TQ.data_ptr(), pq, nQ, int(k), int(n_cand), ids.data_ptr(),
+                          dist.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+        return ids, dist
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _torch().cuda.synchronize()
+            load_library().twed_knn_index_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -127,6 +127,10 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
             a = pairs[2 * item];
             b = pairs[2 * item + 1];
         }
+        // a pair-list entry outside the collections yields NaN (swept as (0, 0))
+        const bool ok = a >= 0 && a < nX && b >= 0 && b < nY;
+        a = ok ? a : 0;
+        b = ok ? b : 0;
         const int64_t xa = offX[a], la = offX[a + 1] - xa;
         const int64_t yb = offY[b], lb = offY[b + 1] - yb;
         const CT *ra = rowsX + (xa + a) * S;
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
                 D[a * nX + b] = d;
                 D[b * nX + a] = d;
             } else {
-                D[item] = d;
+                D[item] = ok ? d : (AT)__builtin_nan("");
             }
         }
     }

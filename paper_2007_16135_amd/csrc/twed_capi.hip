@@ -5,6 +5,7 @@
 // HIP call (section "Time Warp Edit Distance" fixes what a valid problem is:
 // two non-empty series with timestamps, nu >= 0, lambda >= 0, an Lp degree).
 #include "../../include/twed.h"
+#include "capi_util.h"
 #include "twed_kernels.h"
 
 #include <algorithm>
@@ -17,65 +18,21 @@
 #include <vector>
 
 using namespace twed;
+using namespace twed::capi;
+
+namespace twed {
+namespace capi {
+std::string &last_error()
+{
+    thread_local std::string msg;
+    return msg;
+}
+}  // namespace capi
+}  // namespace twed
 
 namespace {
 
-thread_local std::string g_last_error;
-
-twed_status fail(twed_status s, const char *msg)
-{
-    g_last_error = msg;
-    return s;
-}
-
-twed_status fail_hip(hipError_t e, const char *where)
-{
-    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
-    return TWED_ERR_DEVICE;
-}
-
-constexpr size_t kAlign = 256;
-constexpr int64_t kMaxLen = (int64_t(1) << 31) - 2 * 64 - 2;
 constexpr int64_t kDefaultAcc64Threshold = 100000;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Sequential carve-out of the caller's workspace.
-struct Carver {
-    char *base;
-    size_t used = 0;
-    void *take(size_t bytes)
-    {
-        void *p = base ? base + used : nullptr;
-        used += align_up(bytes);
-        return p;
-    }
-};
-
-// Packed rows with kRowPad zero rows on each side; returns the row-0 pointer.
-void *take_rows(Carver &c, Prec prec, int dimt, int64_t rows)
-{
-    char *p = (char *)c.take(rows_bytes(prec, dimt, rows));
-    return p ? p + (size_t)kRowPad * (size_t)row_stride(prec, dimt) * cost_size(prec) : nullptr;
-}
-
-bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
-
-twed_status check_params(const twed_params *prm)
-{
-    if (!prm) return fail(TWED_ERR_INVALID, "params is NULL");
-    if (!finite_nonneg(prm->nu)) return fail(TWED_ERR_INVALID, "nu must be finite and >= 0");
-    if (!finite_nonneg(prm->lambda)) return fail(TWED_ERR_INVALID, "lambda must be finite and >= 0");
-    if (!std::isfinite(prm->p) || prm->p < 1.0) return fail(TWED_ERR_INVALID, "p must be finite and >= 1");
-    if (prm->dim < 1) return fail(TWED_ERR_INVALID, "dim must be >= 1");
-    if (prm->dim > TWED_MAX_DIM) return fail(TWED_ERR_UNSUPPORTED, "dim exceeds TWED_MAX_DIM");
-    if (prm->precision < TWED_F64 || prm->precision > TWED_AUTO)
-        return fail(TWED_ERR_INVALID, "unknown precision");
-    if (prm->algo < TWED_ALGO_AUTO || prm->algo > TWED_ALGO_DIAGONAL) return fail(TWED_ERR_INVALID, "unknown algo");
-    if (!(prm->strip_k == 0 || prm->strip_k == 1 || prm->strip_k == 2 || prm->strip_k == 4 || prm->strip_k == 8))
-        return fail(TWED_ERR_INVALID, "strip_k must be 0, 1, 2, 4 or 8");
-    return TWED_OK;
-}
 
 // Resolved arithmetic of a call whose longest series has `maxlen` samples.
 Prec resolve(const twed_params *prm, int64_t maxlen)
@@ -94,18 +51,6 @@ Prec resolve(const twed_params *prm, int64_t maxlen)
 // AUTO always returns f64; when it resolves to F32 the kernels write f32 into
 // the workspace and a widening pass copies them out.
 bool needs_widen(const twed_params *prm, Prec p) { return prm->precision == TWED_AUTO && p == kF32; }
-
-CostParams cost_params(const twed_params *prm)
-{
-    CostParams cp;
-    cp.nu = prm->nu;
-    cp.lambda = prm->lambda;
-    cp.p = prm->p;
-    cp.dim = prm->dim;
-    cp.dimt = dimt_for(prm->dim);
-    cp.pm = prm->dim == 1 ? 0 : (prm->p == 1.0 ? 0 : (prm->p == 2.0 ? 1 : 2));
-    return cp;
-}
 
 int device_simds()
 {
@@ -167,14 +112,6 @@ PairLayout pair_layout(char *base, int64_t nA, int64_t nB, const twed_params *pr
     L.tmp_out = c.take(8);
     L.total = c.used;
     return L;
-}
-
-twed_status check_workspace(void *ws, size_t ws_bytes, size_t need)
-{
-    if (need > ws_bytes) return fail(TWED_ERR_WORKSPACE, "workspace smaller than the *_workspace_size() value");
-    if (!ws) return fail(TWED_ERR_WORKSPACE, "workspace is NULL");
-    if (((uintptr_t)ws) % kAlign) return fail(TWED_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    return TWED_OK;
 }
 
 // Runs the sweep of one pair whose rows are already staged.
@@ -290,23 +227,6 @@ twed_status pair_impl(const void *A, const void *TA, int64_t nA, const void *B, 
 
 // ---- batch ----------------------------------------------------------------------
 
-twed_status check_offsets(const int64_t *off, int64_t n, int64_t *maxlen, int64_t *total)
-{
-    if (!off) return fail(TWED_ERR_INVALID, "NULL offsets");
-    if (n < 1) return fail(TWED_ERR_INVALID, "collection must hold at least one series");
-    if (off[0] != 0) return fail(TWED_ERR_INVALID, "offsets must start at 0");
-    int64_t mx = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t len = off[i + 1] - off[i];
-        if (len < 1) return fail(TWED_ERR_INVALID, "every series must hold at least one sample");
-        mx = std::max(mx, len);
-    }
-    if (mx > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
-    *maxlen = mx;
-    *total = off[n];
-    return TWED_OK;
-}
-
 struct BatchLayout {
     void *rowsX, *rowsY, *offX, *offY, *order, *zero, *bnd, *flags, *tmpD;
     size_t total;
@@ -365,7 +285,7 @@ size_t twed_pair_workspace_size(int64_t nA, int64_t nB, const twed_params *prm)
 twed_status twed_pair(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
                       const twed_params *prm, void *out, void *workspace, size_t ws_bytes, hipStream_t stream)
 {
-    g_last_error.clear();
+    last_error().clear();
     return pair_impl(A, TA, nA, B, TB, nB, prm, out, nullptr, workspace, ws_bytes, stream);
 }
 
@@ -373,7 +293,7 @@ twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA, const vo
                              const twed_params *prm, void *out, void *dp, void *workspace, size_t ws_bytes,
                              hipStream_t stream)
 {
-    g_last_error.clear();
+    last_error().clear();
     if (!dp) return fail(TWED_ERR_INVALID, "dp is NULL");
     return pair_impl(A, TA, nA, B, TB, nB, prm, out, dp, workspace, ws_bytes, stream);
 }
@@ -409,7 +329,7 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
                        const void *TY, const int64_t *offY, int64_t nY, const int64_t *pairs, int64_t nPairs,
                        const twed_params *prm, void *D, void *workspace, size_t ws_bytes, hipStream_t st)
 {
-    g_last_error.clear();
+    last_error().clear();
     twed_status s = check_params(prm);
     if (s != TWED_OK) return s;
     if (!X || !TX || !D) return fail(TWED_ERR_INVALID, "NULL array argument");
@@ -552,11 +472,11 @@ const char *twed_status_string(twed_status s)
     }
 }
 
-const char *twed_last_error(void) { return g_last_error.c_str(); }
+const char *twed_last_error(void) { return last_error().c_str(); }
 
 twed_status twed_stream_check(hipStream_t stream)
 {
-    g_last_error.clear();
+    last_error().clear();
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail_hip(e, "stream synchronize");
     e = hipGetLastError();

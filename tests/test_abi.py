@@ -11,7 +11,7 @@ import paper_2007_16135_amd as tw
 from paper_2007_16135_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "twed.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("twed.h", "twed_knn.h")]
 
 INVALID, UNSUPPORTED, WORKSPACE = binding.TWED_ERR_INVALID, binding.TWED_ERR_UNSUPPORTED, binding.TWED_ERR_WORKSPACE
 
@@ -22,7 +22,7 @@ def L():
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(twed_[a-z0-9_]+)\s*\(", src)))
 
@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported(L):
     names = declared_functions()
     assert "twed_pair" in names and "twed_batch" in names
     for n in names:
-        assert hasattr(L, n), f"{n} declared in twed.h but not exported"
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
     assert set(binding.EXPORTS) <= set(names)
 
 
@@ -150,3 +150,52 @@ def test_batch_max_short_length(L):
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError, match="not built"):
         binding.load_library(str(tmp_path / "nope.so"))
+
+
+def test_embed_and_knn_host_checks(L):
+    import ctypes as C
+    from oracle import cnn as ocnn
+    assert L.twed_embed_param_count() == ocnn.n_params()
+    assert L.twed_embed_max_length() == 65535
+    off = np.array([0, 5, 9], dtype=np.int64)
+    po = off.ctypes.data_as(C.POINTER(C.c_int64))
+    assert L.twed_embed_workspace_size(po, 2, 0) > 0
+    assert L.twed_embed_workspace_size(po, 2, 10) > L.twed_embed_workspace_size(po, 2, 0)
+    bad = np.array([1, 5, 9], dtype=np.int64)
+    assert L.twed_embed_workspace_size(bad.ctypes.data_as(C.POINTER(C.c_int64)), 2, 0) == 0
+    long_ = np.array([0, 70000], dtype=np.int64)
+    assert L.twed_embed_workspace_size(long_.ctypes.data_as(C.POINTER(C.c_int64)), 1, 0) == 0
+    fake = C.c_void_p(0x100000)
+    assert L.twed_embed_forward(None, fake, po, 2, fake, fake, 1 << 30, None) == INVALID
+    assert L.twed_embed_loss_grad(fake, fake, po, 2, fake, fake, 0, fake, fake, None, fake, 1 << 30,
+                                  None) == INVALID
+    assert L.twed_embed_adamw(fake, fake, fake, fake, 0, 1e-3, 0.0, None) == INVALID
+    assert L.twed_embed_adamw(fake, fake, fake, fake, 1, -1.0, 0.0, None) == INVALID
+    ws = C.c_size_t(L.twed_embed_workspace_size(po, 2, 0))
+    assert L.twed_embed_forward(fake, fake, po, 2, fake, None, ws, None) == WORKSPACE
+    assert L.twed_embed_forward(fake, fake, po, 2, fake, C.c_void_p(0x100010), ws, None) == WORKSPACE
+
+    prm = binding.make_params(1e-3, 1.0, 1.0, 1, "f32")
+    need = L.twed_knn_index_storage_size(po, 2, C.byref(prm))
+    assert need > 0
+    for bad_prm in (binding.make_params(1e-3, 1.0, 1.0, 2, "f32"), binding.make_params(1e-3, 1.0, 1.0, 1, "f64")):
+        assert L.twed_knn_index_storage_size(po, 2, C.byref(bad_prm)) == 0
+        h = C.c_void_p()
+        assert L.twed_knn_index_create(fake, fake, po, 2, fake, C.byref(bad_prm), fake, need,
+                                       C.byref(h)) == UNSUPPORTED
+    h = C.c_void_p()
+    assert L.twed_knn_index_create(None, fake, po, 2, fake, C.byref(prm), fake, need, C.byref(h)) == INVALID
+    assert L.twed_knn_index_create(fake, fake, po, 2, fake, C.byref(prm), fake, need - 1, C.byref(h)) == WORKSPACE
+    # host-only creation with placeholder device addresses: nothing touches the device
+    assert L.twed_knn_index_create(fake, fake, po, 2, fake, C.byref(prm), fake, need, C.byref(h)) == 0
+    assert h.value
+    assert L.twed_knn_index_build_workspace_size(h) > 0
+    offq = np.array([0, 4], dtype=np.int64)
+    pq = offq.ctypes.data_as(C.POINTER(C.c_int64))
+    assert L.twed_knn_workspace_size(h, pq, 1, 1, 2) > 0
+    assert L.twed_knn_workspace_size(h, pq, 1, 3, 2) == 0  # k > n_cand
+    assert L.twed_knn_workspace_size(h, pq, 1, 1, 3) == 0  # n_cand > nDB
+    ids = C.c_void_p(0x200000)
+    assert L.twed_knn(h, fake, fake, pq, 1, 1, 2, ids, ids, fake, 1 << 30, None) == INVALID  # not built
+    assert L.twed_knn(None, fake, fake, pq, 1, 1, 2, ids, ids, fake, 1 << 30, None) == INVALID
+    L.twed_knn_index_destroy(h)

@@ -87,3 +87,22 @@ def test_flatten_roundtrip():
     q = cnn.unflatten(cnn.flatten(p))
     for l in range(4):
         assert np.array_equal(p["W"][l], q["W"][l]) and np.array_equal(p["b"][l], q["b"][l])
+
+
+def test_adamw_first_step_is_signed_lr():
+    # at step 1 the bias-corrected ratio m_hat / sqrt(v_hat) is g / |g| exactly
+    # (up to eps), so each weight moves by lr against the gradient's sign
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    w1, m1, v1 = cnn.adamw_step(w, np.zeros(50), np.zeros(50), g, 1, 1e-2, 0.0, eps=0.0)
+    np.testing.assert_allclose(w1, w - 1e-2 * np.sign(g), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v1, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adamw_decay_only():
+    # zero gradient and zero moments: only the decoupled decay acts
+    w = np.linspace(-1, 1, 9)
+    w1, _, _ = cnn.adamw_step(w, np.zeros(9), np.zeros(9), np.zeros(9), 3, 0.1, 0.5)
+    np.testing.assert_allclose(w1, w * (1 - 0.05), rtol=1e-15)
