@@ -76,7 +76,9 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=30000, help="prefix length of the CPU oracle sample")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (counter calibration)")
-    ap.add_argument("--no-knn", action="store_true", help="skip the learned k-NN measurement")
+    ap.add_argument("--knn", action="store_true",
+                    help="also run the learned k-NN measurement (off by default: its 1e5-series "
+                         "database run faulted the GPU once and the cause is not yet found)")
     ap.add_argument("--knn-db", type=int, default=100_000, help="k-NN database size")
     ap.add_argument("--knn-queries", type=int, default=10_000, help="k-NN queries timed")
     ap.add_argument("--knn-truth", type=int, default=1000,
@@ -113,7 +115,8 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
     DB, TDB, Q, TQ = f32(db.X), f32(db.T), f32(qs.X), f32(qs.T)
     dbc = knn.Collection(DB, TDB, db.off)
 
-    tr = knn.Trainer(dbc, nu, lam, seed=0, batch_series=256, pairs_per_step=2048, refresh=100)
+    tr = knn.Trainer(dbc, nu, lam, seed=0, batch_series=256, pairs_per_step=2048, n_anchors=1024)
+    log(f"knn: exact neighbours of 1024 anchors mined in {tr.mine_s:.1f} s")
     train_s = tr.train(args.knn_train_steps, log_every=100, log=log)
     params = tr.params.clone()
     t0 = time.perf_counter()
@@ -171,7 +174,8 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
     q200 = qps(200)
     out = {"workload": f"{args.knn_db} database / {args.knn_queries} query 1-D FP32 series, lengths U[128,512], "
                        f"half random walks, half noisy sinusoids of 8 classes; nu=1e-3, lambda=1, L1; k=10",
-           "train_pairs": tr.pairs_seen, "train_s": round(train_s, 2), "index_build_s": round(build_s, 3),
+           "train_pairs_labelled": tr.pairs_seen, "train_steps": args.knn_train_steps,
+           "mine_s": round(tr.mine_s, 2), "train_s": round(train_s, 2), "index_build_s": round(build_s, 3),
            "recall_sample_queries": nt, "recall_curve": {str(c): round(r, 4) for c, r in curve.items()},
            "recall@10_at_200": round(curve[200], 4), "queries_per_s_at_200": round(q200, 1),
            "exhaustive_queries_per_s": round(exh_qps, 1), "ablation_recall@10": {
@@ -285,7 +289,7 @@ def main():
         log(f"batch: {result['batched_all_pairs']}")
 
     # ---- learned k-NN: train, index, query; recall against exhaustive TWED
-    if not args.no_knn:
+    if args.knn:
         result["knn"] = knn_bench(args, torch, tw, synth, dev, time_steps)
 
     # ---- CPU oracle on a bounded sample (prefix of the headline pair)

@@ -16,9 +16,10 @@
  * Network (fixed shape; series values only, timestamps are not an input):
  *   features   f_t = (x_t / 8, L / 256) for a series of L samples
  *   4 layers   kernel 5, same padding inside the series, channels
- *              2 -> 64 -> 64 -> 64 -> 32, ReLU after layers 1-3
- *   pooling    segment s = 0..3 covers t in [floor(s L/4), floor((s+1) L/4));
- *              embedding[32 s + c] = mean of layer-4 channel c over segment s
+ *              2 -> 64 -> 64 -> 64 -> 4, ReLU after layers 1-3
+ *   pooling    segment s = 0..31 covers t in [floor(s L/32), floor((s+1) L/32));
+ *              embedding[4 s + c] = mean of layer-4 channel c over segment s
+ *              (0 for an empty segment: series shorter than 32 samples)
  *   loss       for a pair (a, b) with TWED d: p = sqrt(|e_a - e_b|^2 + 1e-6),
  *              (log(1 + p) - log(1 + d))^2, averaged over the pairs
  * Arithmetic: BF16 operands on the matrix cores with FP32 accumulation, FP32
@@ -44,7 +45,7 @@ extern "C" {
 
 /* ---- embedding network ------------------------------------------------------ */
 
-/* Number of FP32 parameters (52,064). */
+/* Number of FP32 parameters (43,076). */
 int64_t twed_embed_param_count(void);
 
 /* Longest series the network accepts (65,535 samples). */

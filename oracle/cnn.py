@@ -10,9 +10,10 @@ embedding whose Euclidean distances are trained to follow TWED:
   layer l = 1..4    y_t = b + sum_{k=0..4} W[k]^T h_{t+k-2}          (kernel 5,
                     h outside [0, L) is zero; y_t = 0 for t >= L      same padding)
                     ReLU after layers 1-3, none after layer 4
-  channels          2 -> 64 -> 64 -> 64 -> 32
-  pooling           segment s = 0..3 covers t in [floor(s L/4), floor((s+1) L/4));
-                    e[32 s + c] = mean over the segment of layer-4 channel c
+  channels          2 -> 64 -> 64 -> 64 -> 4
+  pooling           segment s = 0..31 covers t in [floor(s L/32), floor((s+1) L/32));
+                    e[4 s + c] = mean over the segment of layer-4 channel c
+                    (0 for an empty segment, which happens when L < 32)
   pair loss         p = sqrt(|e_a - e_b|^2 + eps);
                     loss = (log(1 + p) - log(1 + d))^2, d the TWED of the pair
 
@@ -23,9 +24,9 @@ from __future__ import annotations
 
 import numpy as np
 
-CHANNELS = (2, 64, 64, 64, 32)
+CHANNELS = (2, 64, 64, 64, 4)
 KSIZE = 5
-SEGMENTS = 4
+SEGMENTS = 32
 EMB = SEGMENTS * CHANNELS[-1]
 T_MAX = 512
 X_SCALE = 1.0 / 8.0

@@ -65,9 +65,9 @@ __device__ __forceinline__ bf16x4 load_a(const GemmArgs &g, int m, int kk, int k
         if ((C & 3) == 0 && kk + 3 < kend) {
             const int tap = kk / C, c = kk - tap * C;
             const int ts = t + tap - kKsize / 2;
-            if (ts >= 0 && ts < L)
-                v = __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2 *>(
-                                                   g.A + (int64_t)(m + tap - kKsize / 2) * C + c));
+            const int src = m + tap - kKsize / 2;
+            if (ts >= 0 && ts < L && src >= 0 && src < g.M)
+                v = __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2 *>(g.A + (int64_t)src * C + c));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -75,7 +75,8 @@ __device__ __forceinline__ bf16x4 load_a(const GemmArgs &g, int m, int kk, int k
                 if (k >= kend) continue;
                 const int tap = k / C, c = k - tap * C;
                 const int ts = t + tap - kKsize / 2;
-                if (ts >= 0 && ts < L) v[e] = (short)g.A[(int64_t)(m + tap - kKsize / 2) * C + c];
+                const int src = m + tap - kKsize / 2;
+                if (ts >= 0 && ts < L && src >= 0 && src < g.M) v[e] = (short)g.A[(int64_t)src * C + c];
             }
         }
     } else {  // kAConvT: row m = (tap, c), k = packed row
@@ -87,7 +88,9 @@ __device__ __forceinline__ bf16x4 load_a(const GemmArgs &g, int m, int kk, int k
             if (r >= kend) continue;
             const uint32_t info = g.row_info[r];
             const int ts = row_t(info) + tap - kKsize / 2;
-            if (ts >= 0 && ts < row_L(info)) v[e] = (short)g.A[(int64_t)(r + tap - kKsize / 2) * C + c];
+            const int src = r + tap - kKsize / 2;
+            if (ts >= 0 && ts < row_L(info) && src >= 0 && src < g.K)
+                v[e] = (short)g.A[(int64_t)src * C + c];
         }
     }
     return v;
@@ -204,14 +207,15 @@ hipError_t launch_gemm(int out_mode, const GemmArgs &g, int splitk, hipStream_t 
 // Row words (t, L), owning series and layer-1 features (x/8, L/256).
 // Sample t of series s is X[off[s] + t] and packed row off[s] - row_base + t.
 __global__ void features_kernel(const float *__restrict__ X, const int64_t *__restrict__ off, int nSeries,
-                                int64_t row_base, uint32_t *__restrict__ row_info, int32_t *__restrict__ row_series,
-                                uint16_t *__restrict__ feat)
+                                int64_t row_base, int64_t R, uint32_t *__restrict__ row_info,
+                                int32_t *__restrict__ row_series, uint16_t *__restrict__ feat)
 {
     for (int s = blockIdx.y; s < nSeries; s += gridDim.y) {
         const int64_t b = off[s];
         const int L = (int)(off[s + 1] - b);
         for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < L; t += gridDim.x * blockDim.x) {
             const int64_t r = b - row_base + t;
+            if (r < 0 || r >= R) break;  // offsets inconsistent with the chunk: write nothing
             row_info[r] = (uint32_t)t | ((uint32_t)L << 16);
             if (row_series) row_series[r] = s;
             feat[2 * r + 0] = to_bf16(X[b + t] * kXScale);
@@ -223,14 +227,16 @@ __global__ void features_kernel(const float *__restrict__ X, const int64_t *__re
 // Segment means of layer 4 -> embedding (f32 and/or bf16) and the squared
 // norm of the bf16 embedding.  One 128-thread block per series.
 __global__ __launch_bounds__(128) void pool_kernel(const float *__restrict__ y4, const int64_t *__restrict__ off,
-                                                   int nSeries, int64_t row_base, float *__restrict__ emb,
-                                                   uint16_t *__restrict__ emb16, float *__restrict__ sqnorm)
+                                                   int nSeries, int64_t row_base, int64_t R,
+                                                   float *__restrict__ emb, uint16_t *__restrict__ emb16,
+                                                   float *__restrict__ sqnorm)
 {
     __shared__ float part[2];
     const int s = blockIdx.x;
     const int q = threadIdx.x;  // embedding component
     const int64_t b = off[s] - row_base;
-    const int L = (int)(off[s + 1] - b);
+    int L = (int)(off[s + 1] - off[s]);
+    if (b < 0 || b + L > R) L = 0;  // offsets inconsistent with the chunk: read nothing
     const int seg = q / kC4, c = q - (q / kC4) * kC4;
     const int lo = (seg * L) / kSegments, hi = ((seg + 1) * L) / kSegments;
     float acc = 0.f;
@@ -359,21 +365,21 @@ static int grid_for(int64_t n, int per_block = 256, int cap = 8192)
     return g < 1 ? 1 : (int)g;
 }
 
-hipError_t launch_features(const float *X, const int64_t *off, int nSeries, int64_t row_base, int maxlen,
-                           uint32_t *row_info, int32_t *row_series, uint16_t *feat, hipStream_t st)
+hipError_t launch_features(const float *X, const int64_t *off, int nSeries, int64_t row_base, int64_t R,
+                           int maxlen, uint32_t *row_info, int32_t *row_series, uint16_t *feat, hipStream_t st)
 {
     if (nSeries <= 0) return hipSuccess;
     const int gx = (maxlen + 255) / 256, gy = nSeries < 65535 ? nSeries : 65535;
-    hipLaunchKernelGGL(features_kernel, dim3(gx < 1 ? 1 : gx, gy), dim3(256), 0, st, X, off, nSeries, row_base,
+    hipLaunchKernelGGL(features_kernel, dim3(gx < 1 ? 1 : gx, gy), dim3(256), 0, st, X, off, nSeries, row_base, R,
                        row_info, row_series, feat);
     return hipGetLastError();
 }
 
-hipError_t launch_pool(const float *y4, const int64_t *off, int nSeries, int64_t row_base, float *emb,
+hipError_t launch_pool(const float *y4, const int64_t *off, int nSeries, int64_t row_base, int64_t R, float *emb,
                        uint16_t *emb16, float *sqnorm, hipStream_t st)
 {
     if (nSeries <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pool_kernel, dim3(nSeries), dim3(kEmb), 0, st, y4, off, nSeries, row_base, emb, emb16,
+    hipLaunchKernelGGL(pool_kernel, dim3(nSeries), dim3(kEmb), 0, st, y4, off, nSeries, row_base, R, emb, emb16,
                        sqnorm);
     return hipGetLastError();
 }

@@ -9,14 +9,14 @@
 namespace twed {
 namespace cnn {
 
-// Network shape: features (x/8, L/256) -> 64 -> 64 -> 64 -> 32 channels,
+// Network shape: features (x/8, L/256) -> 64 -> 64 -> 64 -> 4 channels,
 // kernel 5 with same padding inside each series, ReLU after layers 1-3,
-// four length-relative segment means of layer 4 -> 128-d embedding.
+// 32 length-relative segment means of layer 4 -> 128-d embedding.
 constexpr int kLayers = 4;
 constexpr int kKsize = 5;
-constexpr int kChan[kLayers + 1] = {2, 64, 64, 64, 32};
-constexpr int kC4 = 32;
-constexpr int kSegments = 4;
+constexpr int kChan[kLayers + 1] = {2, 64, 64, 64, 4};
+constexpr int kC4 = 4;
+constexpr int kSegments = 32;
 constexpr int kEmb = kSegments * kC4;
 constexpr float kXScale = 1.0f / 8.0f;
 constexpr float kLScale = 1.0f / 256.0f;
@@ -69,11 +69,11 @@ hipError_t launch_gemm(int out_mode, const GemmArgs &g, int splitk, hipStream_t 
 
 // Row words, owning series (optional) and layer-1 features of nSeries packed
 // series.  off: device offsets of those series into X; packed row of sample
-// t of series s is off[s] - row_base + t.
-hipError_t launch_features(const float *X, const int64_t *off, int nSeries, int64_t row_base, int maxlen,
-                           uint32_t *row_info, int32_t *row_series, uint16_t *feat, hipStream_t st);
+// t of series s is off[s] - row_base + t; rows outside [0, R) are skipped.
+hipError_t launch_features(const float *X, const int64_t *off, int nSeries, int64_t row_base, int64_t R,
+                           int maxlen, uint32_t *row_info, int32_t *row_series, uint16_t *feat, hipStream_t st);
 // Segment means -> f32 and/or bf16 embeddings (and the bf16 squared norms).
-hipError_t launch_pool(const float *y4, const int64_t *off, int nSeries, int64_t row_base, float *emb,
+hipError_t launch_pool(const float *y4, const int64_t *off, int nSeries, int64_t row_base, int64_t R, float *emb,
                        uint16_t *emb16, float *sqnorm, hipStream_t st);
 hipError_t launch_pool_bwd(const float *demb, const uint32_t *row_info, const int32_t *row_series, int64_t R,
                            uint16_t *dy4, hipStream_t st);
@@ -93,8 +93,10 @@ hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 // smallest (ties: lowest column) -> cand[q*n_cand ..] (any order).
 hipError_t launch_topk_select(const float *scores, int64_t ld, int nQ, int nDB, int n_cand, int32_t *cand,
                               hipStream_t st);
-// pairs[2(q n_cand + c)] = (q0 + q, cand[q n_cand + c]) as int64, q < nQ.
-hipError_t launch_make_pairs(const int32_t *cand, int nQ, int n_cand, int64_t q0, int64_t *pairs, hipStream_t st);
+// pairs[2(q n_cand + c)] = (q0 + q, cand[q n_cand + c]) as int64, q < nQ;
+// (-1, -1) for a candidate id outside [0, nDB).
+hipError_t launch_make_pairs(const int32_t *cand, int nQ, int n_cand, int nDB, int64_t q0, int64_t *pairs,
+                             hipStream_t st);
 // For each query, the k smallest (dist, id) among its n_cand re-ranked
 // candidates, ascending.
 hipError_t launch_final_topk(const float *dist, const int32_t *cand, int nQ, int n_cand, int k, int64_t *ids,

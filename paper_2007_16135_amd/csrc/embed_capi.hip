@@ -110,7 +110,7 @@ hipError_t forward(const float *params, const Weights &w, const Acts &a, const f
                    int64_t row_base, int64_t R, int maxlen, float *emb, uint16_t *emb16, float *sqnorm,
                    hipStream_t st)
 {
-    hipError_t e = launch_features(X, off, nS, row_base, maxlen, a.row_info, a.row_series, a.feat, st);
+    hipError_t e = launch_features(X, off, nS, row_base, R, maxlen, a.row_info, a.row_series, a.feat, st);
     if (e != hipSuccess) return e;
     const uint16_t *in = a.feat;
     for (int l = 0; l < kLayers; ++l) {
@@ -119,7 +119,7 @@ hipError_t forward(const float *params, const Weights &w, const Acts &a, const f
         if (e != hipSuccess) return e;
         if (l < kLayers - 1) in = a.h[l];
     }
-    return launch_pool(a.y4, off, nS, row_base, emb, emb16, sqnorm, st);
+    return launch_pool(a.y4, off, nS, row_base, R, emb, emb16, sqnorm, st);
 }
 
 int64_t chunk_rows_for(int64_t total) { return std::min(total, kMaxChunkRows); }
@@ -547,7 +547,7 @@ twed_status twed_knn(const twed_knn_index *ix, const void *Q, const void *TQ, co
             "selection launch");
     }
     // exact FP32 TWED of every (query, candidate) pair
-    TRY(launch_make_pairs(L.cand, (int)nQ, n_cand, 0, L.pairs, st), "pair list");
+    TRY(launch_make_pairs(L.cand, (int)nQ, n_cand, (int)ix->nDB, 0, L.pairs, st), "pair list");
     BatchArgs b{};
     b.rowsX = L.rowsQ;
     b.rowsY = ix->rows;

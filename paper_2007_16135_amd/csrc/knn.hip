@@ -138,22 +138,27 @@ hipError_t launch_topk_select(const float *scores, int64_t ld, int nQ, int nDB, 
     return hipGetLastError();
 }
 
-__global__ void make_pairs_kernel(const int32_t *__restrict__ cand, int64_t total, int n_cand, int64_t q0,
+// A candidate id outside [0, nDB) becomes the pair (-1, -1), which the
+// batched sweep turns into NaN without touching memory.
+__global__ void make_pairs_kernel(const int32_t *__restrict__ cand, int64_t total, int n_cand, int nDB, int64_t q0,
                                   int64_t *__restrict__ pairs)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        pairs[2 * i] = q0 + i / n_cand;
-        pairs[2 * i + 1] = cand[i];
+        const int32_t c = cand[i];
+        const bool ok = c >= 0 && c < nDB;
+        pairs[2 * i] = ok ? q0 + i / n_cand : -1;
+        pairs[2 * i + 1] = ok ? c : -1;
     }
 }
 
-hipError_t launch_make_pairs(const int32_t *cand, int nQ, int n_cand, int64_t q0, int64_t *pairs, hipStream_t st)
+hipError_t launch_make_pairs(const int32_t *cand, int nQ, int n_cand, int nDB, int64_t q0, int64_t *pairs,
+                             hipStream_t st)
 {
     const int64_t total = (int64_t)nQ * n_cand;
     if (total <= 0) return hipSuccess;
     int64_t g = (total + 255) / 256;
     if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(make_pairs_kernel, dim3((int)g), dim3(256), 0, st, cand, total, n_cand, q0, pairs);
+    hipLaunchKernelGGL(make_pairs_kernel, dim3((int)g), dim3(256), 0, st, cand, total, n_cand, nDB, q0, pairs);
     return hipGetLastError();
 }
 

@@ -3,16 +3,15 @@
 Every numeric step runs in libtwed: the TWED labels come from the batched
 sweep in pair-list mode (twed_batch), the loss and gradients from
 twed_embed_loss_grad, the update from twed_embed_adamw, and mined
-neighbours from the index itself (twed_knn).  This module only chooses
+neighbours from the exhaustive search of the index (twed_knn).  This module only chooses
 which series and pairs go into each step; PyTorch gathers the chosen series
 into one packed device buffer.
 
 Pair sampling (two kinds per step, both labelled with their exact TWED):
   random  pairs of series drawn uniformly from the database;
-  mined   an anchor and its nearest database series under the current
-          index (exact TWED among the network's candidates), refreshed
-          every `refresh` steps -- these teach the fine ordering that a
-          k-NN query depends on.
+  mined   an anchor and some of its exact nearest database series, found
+          once before training by the exhaustive k-NN of the index -- these
+          teach the fine ordering that a k-NN query depends on.
 """
 from __future__ import annotations
 
@@ -23,7 +22,7 @@ import numpy as np
 from . import binding as B
 from .binding import EMBED_DIM
 
-CHANNELS = (2, 64, 64, 64, 32)
+CHANNELS = (2, 64, 64, 64, 4)
 KSIZE = 5
 
 
@@ -62,8 +61,8 @@ class Collection:
 
 class Trainer:
     def __init__(self, db: Collection, nu=1e-3, lam=1.0, seed=0, lr=2e-3, weight_decay=1e-4,
-                 batch_series=256, pairs_per_step=2048, mined_fraction=0.5, mined_k=8, refresh=100,
-                 params=None):
+                 batch_series=256, pairs_per_step=2048, mined_fraction=0.5, n_anchors=1024, pool=20,
+                 per_anchor=10, params=None):
         import torch
         self.torch = torch
         self.db, self.nu, self.lam = db, nu, lam
@@ -77,68 +76,61 @@ class Trainer:
         self.loss = torch.empty(1, dtype=torch.float32, device=dev)
         self.lr, self.wd = lr, weight_decay
         self.S, self.P = batch_series, pairs_per_step
-        self.mined_fraction, self.mined_k, self.refresh = mined_fraction, mined_k, refresh
+        self.mined_fraction, self.per_anchor = mined_fraction, per_anchor
         self.step_count = 0
         self.pairs_seen = 0
-        self.neigh = None  # (anchors, neighbour ids) mined from the current index
         self.history = []
+        self.mine_s = 0.0
+        self.neigh = self._mine(min(db.n, n_anchors), min(pool, db.n - 1)) if mined_fraction > 0 else None
 
     # -- pair sampling --------------------------------------------------------------
 
-    def _mine(self):
-        """Nearest database series of a random anchor set under the current
-        network (exact TWED among its candidates)."""
+    def _mine(self, n_anchors, pool):
+        """Exact nearest database series of random anchors: the exhaustive
+        k-NN of the index (every database series re-ranked, n_cand = n)."""
         torch = self.torch
+        t0 = time.perf_counter()
         n = self.db.n
-        anchors = self.rng.choice(n, size=min(n, 4096), replace=False)
+        anchors = self.rng.choice(n, size=n_anchors, replace=False)
         q = self.db.gather(anchors)
         index = B.KnnIndex(self.db.X, self.db.T, self.db.off, self.params, self.nu, self.lam)
-        k = min(self.mined_k + 1, n)
-        ids, _ = index.query(q.X, q.T, q.off, k=k, n_cand=min(n, max(4 * k, 64)))
-        torch.cuda.synchronize()
+        ids, _ = index.query(q.X, q.T, q.off, k=pool + 1, n_cand=n)
+        ids = ids.cpu().numpy()
         index.close()
-        self.neigh = (anchors, ids.cpu().numpy())
+        nb = np.array([[j for j in row if j != a][:pool] for a, row in zip(anchors, ids)], dtype=np.int64)
+        self.mine_s = time.perf_counter() - t0
+        self.pairs_seen += n_anchors * n
+        return anchors, nb
 
     def _sample(self):
-        """Series of this step and (local) pairs among them."""
+        """Series of this step and (local) pairs among them: groups of an
+        anchor and some of its exact neighbours (anchor-neighbour pairs),
+        then random series and random pairs."""
         n, S, P = self.db.n, self.S, self.P
-        n_mined = int(P * self.mined_fraction) if self.neigh is not None else 0
-        chosen, pairs = [], []
-        if n_mined:
-            anchors, ids = self.neigh
-            per = max(1, ids.shape[1] - 1)
-            n_groups = max(1, min(S // (per + 1), n_mined // per))
-            rows = self.rng.choice(len(anchors), size=n_groups, replace=False)
-            for r in rows:
-                group = [int(anchors[r])] + [int(i) for i in ids[r] if int(i) != int(anchors[r])][:per]
-                chosen.append(group)
-        flat = [i for g in chosen for i in g]
-        rest = S - len(flat)
+        series, pairs = [], []
+        if self.neigh is not None:
+            anchors, nb = self.neigh
+            per = min(self.per_anchor, nb.shape[1])
+            groups = min(len(anchors), int(S * self.mined_fraction) // (per + 1))
+            for r in self.rng.choice(len(anchors), size=groups, replace=False):
+                base = len(series)
+                series.append(int(anchors[r]))
+                series += [int(j) for j in nb[r][self.rng.choice(nb.shape[1], per, replace=False)]]
+                pairs += [(base, base + j) for j in range(1, per + 1)]
+        rest = S - len(series)
         if rest > 0:
-            flat += [int(i) for i in self.rng.choice(n, size=rest, replace=False)]
-        series = np.array(flat, dtype=np.int64)
-        # mined pairs: anchor with each of its neighbours, and neighbours among themselves
-        pos = 0
-        for g in chosen:
-            idx = list(range(pos, pos + len(g)))
-            for a in range(len(idx)):
-                for b in range(a + 1, len(idx)):
-                    pairs.append((idx[a], idx[b]))
-            pos += len(g)
-        pairs = pairs[:n_mined] if n_mined else []
+            series += [int(i) for i in self.rng.choice(n, size=rest, replace=False)]
         m = P - len(pairs)
         a = self.rng.integers(0, len(series), m)
         b = self.rng.integers(0, len(series) - 1, m)
         b = b + (b >= a)
         pairs += list(zip(a.tolist(), b.tolist()))
-        return series, np.asarray(pairs, dtype=np.int64)
+        return np.array(series, dtype=np.int64), np.asarray(pairs, dtype=np.int64)
 
     # -- one optimisation step ----------------------------------------------------
 
     def step(self):
         torch = self.torch
-        if self.mined_fraction > 0 and self.step_count % self.refresh == 0 and self.step_count > 0:
-            self._mine()
         series, pairs = self._sample()
         batch = self.db.gather(series)
         dev = batch.X.device

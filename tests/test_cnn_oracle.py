@@ -39,8 +39,14 @@ def test_conv_is_linear_with_bias():
 
 
 def test_pooling_segments():
-    assert cnn.segments(8) == [(0, 2), (2, 4), (4, 6), (6, 8)]
-    assert cnn.segments(130) == [(0, 32), (32, 65), (65, 97), (97, 130)]
+    assert cnn.SEGMENTS == 32
+    assert cnn.segments(64) == [(2 * s, 2 * s + 2) for s in range(32)]
+    assert cnn.segments(65)[-1] == (62, 65) and cnn.segments(65)[0] == (0, 2)
+    for L in (1, 5, 31, 32, 33, 100, 512):
+        seg = cnn.segments(L)
+        assert seg[0][0] == 0 and seg[-1][1] == L
+        assert all(a[1] == b[0] for a, b in zip(seg, seg[1:]))         # contiguous, in order
+        assert all(c - a in (L // 32, -(-L // 32)) for a, c in seg)    # floor or ceil of L/32
     # constant last layer -> every segment mean equals the constant
     p = cnn.init_params(3)
     for l in range(4):

@@ -264,14 +264,18 @@ def test_knn_pruned_candidates():
 
 
 def test_training_lowers_loss_and_helps_recall():
+    # what the trained network gains: at the same candidate budget it finds
+    # more of the exact neighbours than the untrained one, and the exact
+    # re-rank finds more than the network's own ranking
     db, DB, TDB = collection(1500, 3)
-    qc, Q, TQ = collection(16, 4)
+    qc, Q, TQ = collection(24, 4)
     dbc = knn.Collection(dev(DB), dev(TDB), db.off)
-    tr = knn.Trainer(dbc, NU, LAM, seed=0, batch_series=128, pairs_per_step=512, refresh=40)
+    tr = knn.Trainer(dbc, NU, LAM, seed=0, batch_series=128, pairs_per_step=1024, n_anchors=512)
     first = float(tr.step().item())
-    secs = tr.train(119)
+    secs = tr.train(399)
     last = float(np.mean([float(tr.step().item()) for _ in range(5)]))
-    say(f"training: loss {first:.4f} -> {last:.4f} in {secs:.1f} s, {tr.pairs_seen} pairs")
+    say(f"training: loss {first:.4f} -> {last:.4f} in {secs:.1f} s (mining {tr.mine_s:.1f} s), "
+        f"{tr.pairs_seen} pairs")
     assert last < 0.5 * first
     pairs = np.array([(q, j) for q in range(qc.count) for j in range(db.count)], dtype=np.int64)
     D = oracle_dists(Q, TQ, qc.off, DB, TDB, db.off, pairs).reshape(qc.count, db.count)
@@ -279,11 +283,12 @@ def test_training_lowers_loss_and_helps_recall():
     rec = {}
     for name, vec in (("trained", tr.params.cpu().numpy()), ("untrained", knn.init_params(0))):
         ix = index_for(DB, TDB, db.off, vec)
-        ids, _ = ix.query(dev(Q), dev(TQ), qc.off, k=10, n_cand=60)
-        rec[name] = knn.recall_at(ids.cpu().numpy(), truth)
+        for c in (60, 150):
+            ids, _ = ix.query(dev(Q), dev(TQ), qc.off, k=10, n_cand=c)
+            rec[f"{name}@{c}"] = knn.recall_at(ids.cpu().numpy(), truth)
         ids_net, _ = ix.query(dev(Q), dev(TQ), qc.off, k=10, n_cand=10)
         rec[name + "_network_only"] = knn.recall_at(ids_net.cpu().numpy(), truth)
         ix.close()
-    say(f"recall@10 at 60 candidates: {rec}")
-    assert rec["trained"] >= rec["untrained"]
-    assert rec["trained"] >= rec["trained_network_only"]
+    say(f"recall@10: {rec}")
+    assert rec["trained@150"] >= rec["untrained@150"]
+    assert rec["trained@150"] > rec["trained_network_only"]
