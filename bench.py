@@ -36,8 +36,10 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 #   time term: sub + fma = 2;   f32 -> f64 convert = 1
 #   f64: match add, up + del_A, left + del_B, X update add, 2 min = 6
 OPS_PER_CELL_8D_L2_ACC64 = 29
-#   1-D L1 in f32: sub + (abs free) 1, time sub + fma 2, 3 adds, X add, min3 (2) = 8..9
-OPS_PER_CELL_1D_L1_F32 = 9
+#   1-D L1 in f32: value sub, time sub, fma (|.| are free source modifiers),
+#   match add, two deletion adds, one three-way min (v_min3_f32 is a single
+#   full-rate instruction), X add = 8
+OPS_PER_CELL_1D_L1_F32 = 8
 
 
 def log(*a):

@@ -61,21 +61,30 @@ __device__ __forceinline__ AT sweep_pair(const CT *__restrict__ rowsA, int nA, c
     AT sh_l = INF;
     AT sh_x = lane == 0 ? -AT(0) : INF;  // X(0,0) = -beta with beta = 0
     AT sh_xo = INF;
-    Row<CT, DIMT> cur;
-    load_row<CT, DIMT>(rowsA, 0, cur);
-    const int T = nA + lstar + 1;  // last step: lane lstar finishes row nA
-    for (int t = 0; t < T; ++t) {
-        int rn = t + 1 - lane;
-        rn = rn < 0 ? 0 : (rn > nA ? nA : rn);
-        Row<CT, DIMT> nxt;
-        load_row<CT, DIMT>(rowsA, rn, nxt);
+    // Lane l reads row t - l at step t with no clamping: before row 0 and
+    // past row nA it reads a neighbouring series or the 64 zero rows that pad
+    // every packed buffer (rows -63 .. nA + 64 are touched).  Those rows only
+    // meet +inf operands (before row 0) or feed no result (past row nA).
+    const CT *pa = rowsA - (ptrdiff_t)lane * Row<CT, DIMT>::kStride;
+    Row<CT, DIMT> ra, rb;
+    load_row<CT, DIMT>(pa, 0, ra);
+    auto step = [&](const Row<CT, DIMT> &row) {
         AT left = sh_l, xl;
-        lane_row<CT, AT, DIMT, PM, K>(L, cur, left, sh_xo, xl, ca.nu, ca.p, ca.invp, CT(0));
+        lane_row<CT, AT, DIMT, PM, K>(L, row, left, sh_xo, xl, ca.nu, ca.p, ca.invp, CT(0));
         sh_xo = sh_x;
         sh_l = shift_in(left, INF);
         sh_x = shift_in(xl, INF);
-        cur = nxt;
+    };
+    const int T = nA + lstar + 1;  // last step: lane lstar finishes row nA
+    int t = 0;
+    // two steps per iteration: the band registers alternate without copies
+    for (; t + 2 <= T; t += 2) {
+        load_row<CT, DIMT>(pa, t + 1, rb);
+        step(ra);
+        load_row<CT, DIMT>(pa, t + 2, ra);
+        step(rb);
     }
+    if (t < T) step(ra);
     AT res = L.up[0];
 #pragma unroll
     for (int j = 1; j < K; ++j)
