@@ -61,20 +61,22 @@ int device_simds()
 }
 
 // Columns per lane of the wavefront sweep: the widest strip that still
-// leaves about 1.5 strips per SIMD, so the pipeline covers the machine.
-int choose_k(const twed_params *prm, int64_t nB)
+// leaves about 1.5 strips per SIMD, so the pipeline covers the machine, and
+// whose kernel keeps everything in registers (wide strips of high-dimensional
+// or general-Lp sweeps would spill).
+int choose_k(const twed_params *prm, int64_t nB, Prec prec, const CostParams &cp)
 {
     if (prm->strip_k > 0) return prm->strip_k;
     const int64_t want = (int64_t)device_simds() * 3 / 2;
     for (int k : {8, 4, 2}) {
         const int64_t strips = (nB + 64 * k - 1) / (64 * k);
-        if (strips >= want) return k;
+        if (strips >= want && wavefront_scratch_bytes(prec, cp, k, 1) == 0) return k;
     }
     return 1;
 }
 
-// The wavefront pipeline stays off until its cross-wave handoff is shown
-// correct on the device.
+// Single pairs take the wavefront sweep unless the caller asks for the
+// per-diagonal one.
 bool wavefront_enabled() { return true; }
 
 // Words after the per-strip flags in the zeroed region: work ticket, wait
@@ -148,7 +150,7 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     if (!wavefront_enabled())
         return fail(TWED_ERR_UNSUPPORTED, "the wavefront sweep is switched off in this build "
                                           "(an unexplained stall on its first device run is under investigation)");
-    int K = choose_k(prm, nB);
+    int K = choose_k(prm, nB, prec, cp);
     if (dump) {
         // cell dumps exist for narrow strips only (a validation aid)
         if (prm->strip_k > 2) return fail(TWED_ERR_UNSUPPORTED, "twed_pair_matrix takes strip_k 0, 1 or 2");
@@ -166,21 +168,26 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     w.nStrips = (nB + 64 * K - 1) / (64 * K);
     w.out = out;
     w.dump = dump;
-    // Handoff granularity and read protocol; TWED_WAVEFRONT_SYNC="rows,mode"
-    // overrides them for tuning runs.
-    w.chunk_rows = 64;
-    w.sync_mode = 0;
-    if (const char *env = std::getenv("TWED_WAVEFRONT_SYNC")) {
-        int rows = 0, mode = -1;
-        if (std::sscanf(env, "%d,%d", &rows, &mode) == 2 && (rows == 16 || rows == 32 || rows == 64) &&
-            (mode == 0 || mode == 1)) {
-            w.chunk_rows = rows;
-            w.sync_mode = mode;
+    // Strips per workgroup: in-group handoffs go through LDS, one in G
+    // through global memory.  The widest group that still leaves about one
+    // group per CU; cell dumps use single-wave groups.  TWED_WAVEFRONT_GROUP
+    // (1, 4 or 8) overrides the choice for tuning runs.
+    const int64_t cus = std::max(1, device_simds() / 4);
+    w.group = 1;
+    for (int G : {8, 4})
+        if (w.nStrips * 10 >= (int64_t)G * cus * 9) {
+            w.group = G;
+            break;
         }
+    if (dump) w.group = 1;
+    if (const char *env = std::getenv("TWED_WAVEFRONT_GROUP")) {
+        const int G = std::atoi(env);
+        if ((G == 1 || G == 4 || G == 8) && !dump) w.group = G;
     }
-    int workers = wavefront_max_workers(prec, cp, K);
+    const int64_t groups = (w.nStrips + w.group - 1) / w.group;
+    int workers = wavefront_max_workers(prec, cp, K, w.group);
     if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
-    w.grid = (int)std::min<int64_t>(w.nStrips, workers);
+    w.grid = (int)std::min<int64_t>(groups, workers);
     e = launch_wavefront(prec, cp, K, w, st);
     if (e != hipSuccess) return fail_hip(e, "wavefront sweep launch");
     return TWED_OK;

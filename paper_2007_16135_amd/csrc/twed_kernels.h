@@ -54,9 +54,8 @@ struct WavefrontArgs {
     const void *beta;   // one cost element: FP32 cost offset (read in FP32 mode)
     void *out;          // one accumulator element
     void *dump;         // optional (nA+1)*(nB+1) accumulators
-    int grid;           // workgroups (one wave each)
-    int chunk_rows;     // boundary rows per handoff: 16, 32 or 64
-    int sync_mode;      // SyncMode of wavefront.hip
+    int grid;           // workgroups
+    int group;          // waves (consecutive strips) per workgroup: 1, 4 or 8
 };
 hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, hipStream_t st);
 // FP32 pairs longer than this get a per-diagonal cost offset.
@@ -64,8 +63,10 @@ constexpr int64_t kOffsetMinLength = 4096;
 // Writes the FP32 cost offset of one staged pair to beta (one cost element).
 hipError_t launch_offset(Prec prec, const CostParams &cp, const void *rowsA, int64_t nA, const void *rowsB,
                          int64_t nB, void *beta, hipStream_t st);
-// Occupancy-derived worker count for one wavefront instantiation.
-int wavefront_max_workers(Prec prec, const CostParams &cp, int K);
+// Resident workgroups of G waves for one wavefront instantiation.
+int wavefront_max_workers(Prec prec, const CostParams &cp, int K, int G);
+// Per-lane scratch (register spill) bytes of one wavefront instantiation.
+size_t wavefront_scratch_bytes(Prec prec, const CostParams &cp, int K, int G);
 
 // Fills row 0 and column 0 of a dump matrix (0 at the corner, +inf elsewhere).
 hipError_t launch_dump_border(Prec prec, void *dump, int64_t nA, int64_t nB, hipStream_t st);
