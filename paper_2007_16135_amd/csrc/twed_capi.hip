@@ -171,7 +171,8 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     // Strips per workgroup: in-group handoffs go through LDS, one in G
     // through global memory.  The widest group that still leaves about one
     // group per CU; cell dumps use single-wave groups.  TWED_WAVEFRONT_GROUP
-    // (1, 4 or 8) overrides the choice for tuning runs.
+    // (1, 4 or 8) and TWED_WAVEFRONT_SUB (in-group handoff rows: 8, 16 or 32)
+    // override the choices for tuning runs.
     const int64_t cus = std::max(1, device_simds() / 4);
     w.group = 1;
     for (int G : {8, 4})
@@ -183,6 +184,11 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     if (const char *env = std::getenv("TWED_WAVEFRONT_GROUP")) {
         const int G = std::atoi(env);
         if ((G == 1 || G == 4 || G == 8) && !dump) w.group = G;
+    }
+    w.sub_shift = 4;
+    if (const char *env = std::getenv("TWED_WAVEFRONT_SUB")) {
+        const int v = std::atoi(env);
+        if (v == 8 || v == 16 || v == 32) w.sub_shift = v == 8 ? 3 : (v == 16 ? 4 : 5);
     }
     const int64_t groups = (w.nStrips + w.group - 1) / w.group;
     int workers = wavefront_max_workers(prec, cp, K, w.group);

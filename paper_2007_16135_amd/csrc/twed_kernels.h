@@ -56,6 +56,7 @@ struct WavefrontArgs {
     void *dump;         // optional (nA+1)*(nB+1) accumulators
     int grid;           // workgroups
     int group;          // waves (consecutive strips) per workgroup: 1, 4 or 8
+    int sub_shift;      // in-group handoff every 1 << sub_shift rows (3, 4 or 5)
 };
 hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, hipStream_t st);
 // FP32 pairs longer than this get a per-diagonal cost offset.

@@ -41,9 +41,9 @@ struct alignas(2 * sizeof(AT)) Pair2 {
     AT x;
 };
 
-// Steps between two handoffs inside a workgroup, and rows per global handoff
-// (one window of the 64-lane boundary register).
-constexpr int kSub = 16;
+// Rows per global handoff (one window of the 64-lane boundary register).
+// Inside a workgroup the handoff comes every 1 << sub_shift steps (8, 16 or
+// 32; a kernel argument).
 constexpr int kWindow = 64;
 // Rows of one in-group boundary kept in LDS (power of two), plus one slot
 // that absorbs the writes of lanes without a row.
@@ -115,8 +115,9 @@ template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP>
 __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g, int s, const CT *__restrict__ rowsA,
                                             const CT *__restrict__ rowsB, int nA, int nB, const CostArgs<CT> &ca,
                                             Pair2<AT> *bnd, uint32_t *flags, uint32_t *err, int nStrips, CT beta,
-                                            AT *out, AT *dump)
+                                            AT *out, AT *dump, int sub_shift)
 {
+    const int kSub = 1 << sub_shift;
     constexpr int S = Row<CT, DIMT>::kStride;
     constexpr int W = kWave * K;
     const int lane = threadIdx.x & (kWave - 1);
@@ -178,7 +179,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     AT col_dp = INF, col_x = INF;
 
     for (int t0 = 0; t0 < T; t0 += kSub) {
-        const int q = (t0 / kSub) & (kWindow / kSub - 1);  // sub-chunk within the window
+        const int q = (t0 >> sub_shift) & ((kWindow >> sub_shift) - 1);  // sub-chunk within the window
         const int wb = t0 - q * kSub;                          // window start
         const int steps = T - t0 < kSub ? T - t0 : kSub;
         if (in_global && q == 0) {
@@ -196,7 +197,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             const int rr = wb + 1 + lane < nA ? wb + 1 + lane : nA;
             const Pair2<AT> v = sh.ring[w > 0 ? w - 1 : 0][rr & (kRing - 1)];
-            const bool mine = (lane >> 4) == q;  // lanes of this sub-chunk take their rows
+            const bool mine = (lane >> sub_shift) == q;  // lanes of this sub-chunk take their rows
             cdp = mine ? v.dp : cdp;
             cx = mine ? v.x : cx;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -271,7 +272,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
             __hip_atomic_store(&sh.prod[w], (uint32_t)(last < nA ? last : nA), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        if (out_global && (q == kWindow / kSub - 1 || tend >= T)) {
+        if (out_global && (q == (kWindow >> sub_shift) - 1 || tend >= T)) {
             // the window's rows are in lanes kWave - (tend - wb) .. 63 (lanes
             // without a row of this window write slot row 0, which no
             // consumer reads: no lane-conditional branch)
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restri
                                                              const CT *__restrict__ rowsB, int nA, int nB,
                                                              CostArgs<CT> ca, Pair2<AT> *bnd, uint32_t *flags,
                                                              uint32_t *ticket, uint32_t *err, int nStrips,
-                                                             const CT *beta_ptr, AT *out, AT *dump)
+                                                             const CT *beta_ptr, AT *out, AT *dump, int sub_shift)
 {
     __shared__ GroupShared<AT, G> sh;
     const int w = (int)(threadIdx.x / kWave);
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restri
         const int s = g * G + w;
         if (s < nStrips)
             sweep_strip<CT, AT, DIMT, PM, K, G, DUMP>(sh, w, g, s, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
-                                                      nStrips, beta, out, dump);
+                                                      nStrips, beta, out, dump, sub_shift);
     }
 }
 
@@ -337,7 +338,7 @@ static hipError_t launch_kg(const WavefrontArgs &a, const CostParams &cp, hipStr
             hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, G, true>), dim3(a.grid), dim3(kWave * G), 0,
                                st, (const CT *)a.rowsA, (const CT *)a.rowsB, (int)a.nA, (int)a.nB,
                                CostArgs<CT>::make(cp), (Pair2<AT> *)a.bnd, a.flags, a.ticket, a.ticket + 1,
-                               (int)a.nStrips, (const CT *)a.beta, (AT *)a.out, (AT *)a.dump);
+                               (int)a.nStrips, (const CT *)a.beta, (AT *)a.out, (AT *)a.dump, a.sub_shift);
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
@@ -346,7 +347,7 @@ static hipError_t launch_kg(const WavefrontArgs &a, const CostParams &cp, hipStr
     hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, G, false>), dim3(a.grid), dim3(kWave * G), 0, st,
                        (const CT *)a.rowsA, (const CT *)a.rowsB, (int)a.nA, (int)a.nB, CostArgs<CT>::make(cp),
                        (Pair2<AT> *)a.bnd, a.flags, a.ticket, a.ticket + 1, (int)a.nStrips, (const CT *)a.beta,
-                       (AT *)a.out, nullptr);
+                       (AT *)a.out, nullptr, a.sub_shift);
     return hipGetLastError();
 }
 

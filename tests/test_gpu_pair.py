@@ -265,3 +265,32 @@ def test_auto_precision_policy():
     lo = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "auto", acc64_threshold=4000)
     hi = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "auto", acc64_threshold=3999)
     assert lo == f32 and hi == acc
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_acc64"])
+def test_strip_groups_bitwise(prec, monkeypatch):
+    """Workgroups of 1, 4 or 8 strips hand boundaries over through global
+    memory or LDS; the cells and their arithmetic are the same, so results
+    agree to the bit with each other and with the per-diagonal sweep.  The
+    shape gives 13 strips at K=1 (groups 8+5, or 4+4+4+1), 7 at K=2 and 4 at
+    K=4, so full, partial and single-strip groups all occur."""
+    c = synth.random_pair(41, 42, 1400, 64 * 13 - 5, 3, irregular=True, nu=0.02, lam=0.6, p=2.0)
+    ref = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec, algo="diagonal")
+    for k in (1, 2, 4):
+        for g in ("1", "4", "8"):
+            monkeypatch.setenv("TWED_WAVEFRONT_GROUP", g)
+            say(f"groups {prec} K={k} G={g}")
+            v = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec, algo="wavefront", strip_k=k)
+            assert v == ref, (prec, k, g, v, ref)
+
+
+def test_strip_groups_long_pair_vs_oracle(monkeypatch):
+    """A pair long enough for many LDS sub-chunks and global windows, in
+    groups of 8, against the FP64 oracle (FP32 costs with FP64 accumulators)."""
+    c = synth.single_pair_8d(20000).astype(np.float32).astype(np.float64)
+    ref = oracle.twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, rows=True)
+    monkeypatch.setenv("TWED_WAVEFRONT_GROUP", "8")
+    for k in (1, 2):
+        say(f"groups long K={k}")
+        v = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f32_acc64", strip_k=k)
+        assert abs(v - ref) <= 1e-6 * abs(ref), (k, v, ref)
