@@ -123,6 +123,24 @@ twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA,
                              const twed_params *prm, void *out, void *dp,
                              void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* Measures the single-pair sweep configurations (strip width = columns per
+ * lane, strips per workgroup) on this pair -- a prefix of A of up to 262,144
+ * samples against all of B -- and remembers the fastest for this precision,
+ * dimension, distance and nB in a host-side, process-wide cache; later
+ * twed_pair calls with strip_k == 0 and the same key use it.  Arguments as
+ * twed_pair (the same workspace size); the chosen values are written to
+ * *strip_k and *group when those are not NULL.  Synchronises `stream`.
+ * Results never depend on the configuration (every cell is evaluated with
+ * the same arithmetic); only the time does.  Errors as twed_pair, plus
+ * TWED_ERR_INVALID for algo == TWED_ALGO_DIAGONAL. */
+twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA,
+                           const void *B, const void *TB, int64_t nB,
+                           const twed_params *prm, void *workspace, size_t ws_bytes,
+                           hipStream_t stream, int32_t *strip_k, int32_t *group);
+
+/* Empties the tuning cache. */
+void twed_tune_clear(void);
+
 /* ---- many pairs (the paper's batch mode, section "cuTWED Implementation
  * Remarks"; the symmetric case computes only the upper triangle, as the
  * section "Validation using Real Datasets" anticipates) ---------------------

@@ -23,6 +23,7 @@ EXPORTS = [
     "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_matrix",
     "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
+    "twed_pair_tune", "twed_tune_clear",
     "twed_embed_param_count", "twed_embed_max_length", "twed_embed_workspace_size", "twed_embed_forward",
     "twed_embed_loss_grad", "twed_embed_adamw", "twed_knn_index_storage_size", "twed_knn_index_create",
     "twed_knn_index_build_workspace_size", "twed_knn_index_build", "twed_knn_workspace_size", "twed_knn",
@@ -72,6 +73,11 @@ def load_library(path: str = LIB_PATH):
     L.twed_batch.argtypes = [_vp, _vp, _i64p, _i64, _vp, _vp, _i64p, _i64, _vp, _i64, _pp, _vp, _vp,
                              ctypes.c_size_t, _vp]
     L.twed_batch.restype = ctypes.c_int
+    L.twed_pair_tune.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, ctypes.c_size_t, _vp,
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.twed_pair_tune.restype = ctypes.c_int
+    L.twed_tune_clear.argtypes = []
+    L.twed_tune_clear.restype = None
     L.twed_batch_max_short_length.argtypes = [ctypes.c_int32]
     L.twed_batch_max_short_length.restype = ctypes.c_int64
     L.twed_status_string.argtypes = [ctypes.c_int]
@@ -222,6 +228,29 @@ def twed_pair_matrix(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", alg
                               ctypes.byref(prm), out.data_ptr(), dp.data_ptr(), ws.data_ptr(), ws.numel(),
                               _stream(stream)))
     return out, dp
+
+
+def twed_pair_tune(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", acc64_threshold=0, workspace=None,
+                   stream=None):
+    """Times the single-pair sweep configurations on this pair and caches the
+    fastest for later twed_pair calls (strip_k=0).  Returns (strip_k, group)."""
+    dt = input_dtype(precision)
+    A2 = A if A.dim() == 2 else A.reshape(-1, 1)
+    B2 = B if B.dim() == 2 else B.reshape(-1, 1)
+    _dev(A2, dt, "A"); _dev(B2, dt, "B"); _dev(TA, dt, "TA"); _dev(TB, dt, "TB")
+    nA, dim = A2.shape
+    nB = B2.shape[0]
+    prm = make_params(nu, lam, p, dim, precision, "auto", 0, acc64_threshold)
+    L = load_library()
+    ws = _workspace(L.twed_pair_workspace_size(nA, nB, ctypes.byref(prm)), A2.device, workspace)
+    k, g = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(L.twed_pair_tune(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB, ctypes.byref(prm),
+                            ws.data_ptr(), ws.numel(), _stream(stream), ctypes.byref(k), ctypes.byref(g)))
+    return int(k.value), int(g.value)
+
+
+def twed_tune_clear():
+    load_library().twed_tune_clear()
 
 
 def _offsets(off):

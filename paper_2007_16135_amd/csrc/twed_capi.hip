@@ -11,6 +11,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -116,12 +119,47 @@ PairLayout pair_layout(char *base, int64_t nA, int64_t nB, const twed_params *pr
     return L;
 }
 
+// ---- sweep configuration and its tuning cache ---------------------------------------
+//
+// A single-pair sweep is configured by the strip width K (columns per lane),
+// the group size G (strips per workgroup) and the in-group handoff interval.
+// The defaults come from occupancy rules; twed_pair_tune measures the
+// candidates on the caller's own pair and caches the fastest per
+// (precision, dimension, distance, nB), which later calls with strip_k = 0
+// use.
+struct SweepChoice {
+    int K, G, sub_shift;
+};
+
+using TuneKey = std::tuple<int, int, int, int64_t>;
+
+std::mutex &tune_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
+std::map<TuneKey, SweepChoice> &tune_cache()
+{
+    static std::map<TuneKey, SweepChoice> c;
+    return c;
+}
+
+bool tuned_choice(Prec prec, const CostParams &cp, int64_t nB, SweepChoice *out)
+{
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    const auto it = tune_cache().find(TuneKey{(int)prec, cp.dimt, cp.pm, nB});
+    if (it == tune_cache().end()) return false;
+    *out = it->second;
+    return true;
+}
+
 // Runs the sweep of one pair whose rows are already staged.
 // `tail` points at the kTailWords words after the flags (zeroed beforehand).
 twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *prm, const void *rowsA,
                            const void *rowsB, int64_t nA, int64_t nB, void *bnd, uint32_t *flags,
                            uint32_t *tail, const PairLayout *diag_layout, void *out, void *dump,
-                           hipStream_t st)
+                           hipStream_t st, const SweepChoice *force = nullptr)
 {
     hipError_t e;
     void *beta = tail + 2;
@@ -150,7 +188,9 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     if (!wavefront_enabled())
         return fail(TWED_ERR_UNSUPPORTED, "the wavefront sweep is switched off in this build "
                                           "(an unexplained stall on its first device run is under investigation)");
-    int K = choose_k(prm, nB, prec, cp);
+    SweepChoice tuned{};
+    const bool have_tuned = !force && !dump && prm->strip_k == 0 && tuned_choice(prec, cp, nB, &tuned);
+    int K = force ? force->K : (have_tuned ? tuned.K : choose_k(prm, nB, prec, cp));
     if (dump) {
         // cell dumps exist for narrow strips only (a validation aid)
         if (prm->strip_k > 2) return fail(TWED_ERR_UNSUPPORTED, "twed_pair_matrix takes strip_k 0, 1 or 2");
@@ -189,6 +229,14 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     if (const char *env = std::getenv("TWED_WAVEFRONT_SUB")) {
         const int v = std::atoi(env);
         if (v == 8 || v == 16 || v == 32) w.sub_shift = v == 8 ? 3 : (v == 16 ? 4 : 5);
+    }
+    if (have_tuned) {
+        w.group = tuned.G;
+        w.sub_shift = tuned.sub_shift;
+    }
+    if (force) {
+        w.group = force->G;
+        w.sub_shift = force->sub_shift;
     }
     const int64_t groups = (w.nStrips + w.group - 1) / w.group;
     int workers = wavefront_max_workers(prec, cp, K, w.group);
@@ -309,6 +357,83 @@ twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA, const vo
     last_error().clear();
     if (!dp) return fail(TWED_ERR_INVALID, "dp is NULL");
     return pair_impl(A, TA, nA, B, TB, nB, prm, out, dp, workspace, ws_bytes, stream);
+}
+
+twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                           const twed_params *prm, void *workspace, size_t ws_bytes, hipStream_t st,
+                           int32_t *strip_k, int32_t *group)
+{
+    last_error().clear();
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    if (!A || !TA || !B || !TB) return fail(TWED_ERR_INVALID, "NULL array argument");
+    if (nA < 1 || nB < 1) return fail(TWED_ERR_INVALID, "series lengths must be >= 1");
+    if (nA > kMaxLen || nB > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    if (prm->algo == TWED_ALGO_DIAGONAL) return fail(TWED_ERR_INVALID, "only the wavefront sweep is tuned");
+    const Prec prec = resolve(prm, std::max(nA, nB));
+    const PairLayout need = pair_layout(nullptr, nA, nB, prm, prec);
+    s = check_workspace(workspace, ws_bytes, need.total);
+    if (s != TWED_OK) return s;
+    const PairLayout L = pair_layout((char *)workspace, nA, nB, prm, prec);
+    const CostParams cp = cost_params(prm);
+    uint32_t *flags = (uint32_t *)L.zero;
+    uint32_t *tail = flags + L.nflags;
+    hipError_t e;
+    // the cost per row is uniform, so a prefix of A long enough to cover the
+    // pipeline's fill and drain ranks the candidates
+    const int64_t rows = std::min<int64_t>(nA, 262144);
+    e = launch_stage(prec, cp, B, TB, nullptr, 1, nB, nB, nB + 1, L.rowsB, nullptr, 0, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess) {
+        if (ev0) hipEventDestroy(ev0);
+        return fail_hip(e, "event create");
+    }
+    SweepChoice best{0, 0, 4};
+    float best_ms = 0.f;
+    twed_params p1 = *prm;
+    p1.strip_k = 0;
+    for (int K : {8, 4, 2, 1}) {
+        if (wavefront_scratch_bytes(prec, cp, K, 1) != 0) continue;
+        const int64_t strips = (nB + 64 * K - 1) / (64 * K);
+        for (int G : {8, 4, 1}) {
+            if (G > 1 && strips < 2 * G) continue;
+            const SweepChoice c{K, G, 4};
+            // restaging A zeroes the flags and the ticket for this run
+            e = launch_stage(prec, cp, A, TA, nullptr, 1, rows, rows, rows + 1, L.rowsA, flags, L.zero_words, st);
+            if (e == hipSuccess) e = hipEventRecord(ev0, st);
+            if (e != hipSuccess) break;
+            s = run_pair_sweep(prec, cp, &p1, L.rowsA, L.rowsB, rows, nB, L.bnd, flags, tail, &L, L.tmp_out,
+                               nullptr, st, &c);
+            if (s != TWED_OK) break;
+            if ((e = hipEventRecord(ev1, st)) != hipSuccess || (e = hipEventSynchronize(ev1)) != hipSuccess) break;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess) break;
+            if (best.K == 0 || ms < best_ms) {
+                best = c;
+                best_ms = ms;
+            }
+        }
+        if (e != hipSuccess || s != TWED_OK) break;
+    }
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+    if (s != TWED_OK) return s;
+    if (e != hipSuccess) return fail_hip(e, "tuning run");
+    if (best.K == 0) return fail(TWED_ERR_UNSUPPORTED, "no sweep configuration fits this pair");
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        tune_cache()[TuneKey{(int)prec, cp.dimt, cp.pm, nB}] = best;
+    }
+    if (strip_k) *strip_k = best.K;
+    if (group) *group = best.G;
+    return TWED_OK;
+}
+
+void twed_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    tune_cache().clear();
 }
 
 int64_t twed_batch_max_short_length(int32_t dim)

@@ -199,3 +199,20 @@ def test_embed_and_knn_host_checks(L):
     assert L.twed_knn(h, fake, fake, pq, 1, 1, 2, ids, ids, fake, 1 << 30, None) == INVALID  # not built
     assert L.twed_knn(None, fake, fake, pq, 1, 1, 2, ids, ids, fake, 1 << 30, None) == INVALID
     L.twed_knn_index_destroy(h)
+
+
+def test_tune_host_checks(L):
+    import ctypes as C
+    prm = binding.make_params(1e-3, 1.0, 1.0, 1, "f64")
+    fake = C.c_void_p(0x100000)
+    k, g = C.c_int32(0), C.c_int32(0)
+    assert L.twed_pair_tune(None, fake, 10, fake, fake, 10, C.byref(prm), fake, 1 << 30, None,
+                            C.byref(k), C.byref(g)) == INVALID
+    assert L.twed_pair_tune(fake, fake, 0, fake, fake, 10, C.byref(prm), fake, 1 << 30, None,
+                            C.byref(k), C.byref(g)) == INVALID
+    diag = binding.make_params(1e-3, 1.0, 1.0, 1, "f64", algo="diagonal")
+    assert L.twed_pair_tune(fake, fake, 10, fake, fake, 10, C.byref(diag), fake, 1 << 30, None,
+                            C.byref(k), C.byref(g)) == INVALID
+    assert L.twed_pair_tune(fake, fake, 10, fake, fake, 10, C.byref(prm), None, 0, None,
+                            C.byref(k), C.byref(g)) == WORKSPACE
+    L.twed_tune_clear()

@@ -294,3 +294,21 @@ def test_strip_groups_long_pair_vs_oracle(monkeypatch):
         say(f"groups long K={k}")
         v = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f32_acc64", strip_k=k)
         assert abs(v - ref) <= 1e-6 * abs(ref), (k, v, ref)
+
+
+def test_tuner_picks_a_configuration_and_keeps_results():
+    """twed_pair_tune times the sweep configurations and caches the fastest;
+    the tuned call returns the bit-identical distance."""
+    c = synth.random_pair(51, 52, 30000, 20000, 3, irregular=True, nu=0.01, lam=0.5, p=2.0)
+    dt = torch.float64
+    A, TA, B, TB = dev(c.A, dt), dev(c.TA, dt), dev(c.B, dt), dev(c.TB, dt)
+    tw.twed_tune_clear()
+    say("tuner: untuned run")
+    before = float(tw.twed_pair(A, TA, B, TB, c.nu, c.lam, c.p, "f64").item())
+    say("tuner: tuning")
+    k, g = tw.twed_pair_tune(A, TA, B, TB, c.nu, c.lam, c.p, "f64")
+    assert k in (1, 2, 4, 8) and g in (1, 4, 8)
+    say(f"tuner: chose K={k} G={g}")
+    after = float(tw.twed_pair(A, TA, B, TB, c.nu, c.lam, c.p, "f64").item())
+    tw.twed_tune_clear()
+    assert after == before
