@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched all-pairs measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--cpu-n", type=int, default=30000, help="prefix length of the CPU oracle sample")
+    ap.add_argument("--no-rn", action="store_true", help="skip the R^28 single-query measurement")
+    ap.add_argument("--rn-all", action="store_true", help="also time the 60000 x 60000 R^28 all-pairs matrix")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--knn", action="store_true",
@@ -289,6 +291,52 @@ def main():
             "roofline_frac": round(OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / VALU_PEAK_TOPS, 4),
         }
         log(f"batch: {result['batched_all_pairs']}")
+
+    # ---- R^28: one query against 60,000 series of 28 samples in R^28 (FP64, L2)
+    if not args.no_rn:
+        log("generating 60000 x 28 series in R^28")
+        rcol = synth.paper_shaped_rn(60000, 28, 28)
+        rq = rcol.subset([0])
+        f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+        QX, QT, RX, RT = f64(rq.X), f64(rq.T), f64(rcol.X), f64(rcol.T)
+        rprm = tw.make_params(1e-3, 1.0, 2.0, 28, "f64")
+        rD = torch.empty((1, rcol.count), dtype=torch.float64, device=dev)
+        rws = torch.empty(max(tw.twed_batch_workspace_size(rq.off, rcol.off, rprm), 256), dtype=torch.uint8,
+                          device=dev)
+
+        def rstep():
+            tw.twed_batch(QX, QT, rq.off, RX, RT, rcol.off, nu=1e-3, lam=1.0, p=2.0, precision="f64", D=rD,
+                          workspace=rws)
+
+        rsteps = max(args.steps, 10)
+        rwall, rper = time_steps(rstep, rsteps, 2, torch)
+        rcells = 28.0 * 28.0 * rcol.count
+        result["rn_query"] = {
+            "workload": "1 query x 60000 series, 28 samples in R^28 each (seeded Gaussian walks standing in "
+                        "for unravelled 28x28 images), regular times, nu=1e-3, lambda=1, L2, FP64",
+            "ms_per_query": round(rwall / rsteps * 1e3, 4),
+            "kernel_ms": round(float(np.mean(rper)) * 1e3, 4),
+            "GCUPS": round(rcells / float(np.mean(rper)) / 1e9, 3),
+            "paper_gpu_s": 0.20,
+        }
+        log(f"rn query: {result['rn_query']}")
+        if args.rn_all:
+            # the full 60000 x 60000 symmetric matrix (28.8 GB of FP64 output)
+            aD = torch.empty((rcol.count, rcol.count), dtype=torch.float64, device=dev)
+            aws = torch.empty(max(tw.twed_batch_workspace_size(rcol.off, None, rprm), 256),
+                              dtype=torch.uint8, device=dev)
+            log("rn all-pairs 60000 x 60000")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tw.twed_batch(RX, RT, rcol.off, nu=1e-3, lam=1.0, p=2.0, precision="f64", D=aD, workspace=aws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            acells = 28.0 * 28.0 * rcol.count * (rcol.count - 1) / 2
+            result["rn_all_pairs"] = {"workload": "60000 x 60000 symmetric matrix of the same collection "
+                                                  "(upper triangle swept)",
+                                      "seconds": round(dt, 3), "GCUPS": round(acells / dt / 1e9, 3)}
+            log(f"rn all-pairs: {result['rn_all_pairs']}")
+            del aD, aws
 
     # ---- learned k-NN: train, index, query; recall against exhaustive TWED
     if args.knn:

@@ -78,7 +78,7 @@ typedef enum {
                                 series; kept as a cross-check) */
 } twed_algo;
 
-#define TWED_MAX_DIM 16
+#define TWED_MAX_DIM 32
 
 typedef struct {
     double nu;               /* stiffness, >= 0 and finite */
@@ -88,7 +88,8 @@ typedef struct {
     int32_t precision;       /* twed_precision */
     int32_t algo;            /* twed_algo (single pairs only) */
     int32_t strip_k;         /* 0 = auto; else columns per lane of the
-                                wavefront sweep (1, 2, 4 or 8) */
+                                wavefront sweep (1, 2, 4 or 8; 1 or 2 when
+                                dim > 16) */
     int64_t acc64_threshold; /* TWED_AUTO switch-over length; <= 0 means 100000 */
 } twed_params;
 

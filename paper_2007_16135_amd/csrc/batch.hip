@@ -23,13 +23,14 @@ int batch_kmax(int dimt)
     if (dimt <= 1) return 16;
     if (dimt <= 4) return 8;
     if (dimt <= 8) return 4;
-    return 2;
+    if (dimt <= 16) return 2;
+    return 1;
 }
 
 template <int DIMT>
 __host__ __device__ constexpr int kmax_of()
 {
-    return DIMT <= 1 ? 16 : (DIMT <= 4 ? 8 : (DIMT <= 8 ? 4 : 2));
+    return DIMT <= 1 ? 16 : (DIMT <= 4 ? 8 : (DIMT <= 8 ? 4 : (DIMT <= 16 ? 2 : 1)));
 }
 
 // Sweeps one pair with one wave; returns DP(nA, nB) in every lane.  Pairs

@@ -68,6 +68,8 @@ inline twed_status check_params(const twed_params *prm)
     if (prm->algo < TWED_ALGO_AUTO || prm->algo > TWED_ALGO_DIAGONAL) return fail(TWED_ERR_INVALID, "unknown algo");
     if (!(prm->strip_k == 0 || prm->strip_k == 1 || prm->strip_k == 2 || prm->strip_k == 4 || prm->strip_k == 8))
         return fail(TWED_ERR_INVALID, "strip_k must be 0, 1, 2, 4 or 8");
+    if (prm->dim > 16 && prm->strip_k > 2)
+        return fail(TWED_ERR_UNSUPPORTED, "strip_k 4 and 8 are not available for dim > 16");
     return TWED_OK;
 }
 

@@ -17,6 +17,7 @@ int dimt_for(int dim)
     if (dim <= 4) return dim < 1 ? 1 : dim;
     if (dim <= 8) return 8;
     if (dim <= 16) return 16;
+    if (dim <= 32) return 32;
     return -1;
 }
 

@@ -210,13 +210,16 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     w.dump = dump;
     // Strips per workgroup: in-group handoffs go through LDS, one in G
     // through global memory.  The widest group that still leaves about one
-    // group per CU; cell dumps use single-wave groups.  TWED_WAVEFRONT_GROUP
+    // group per CU and whose kernel keeps to registers (eight waves put two
+    // on each SIMD, which halves the registers a lane may hold: too few for
+    // the widest high-dimensional strips); cell dumps use single-wave groups.
+    // TWED_WAVEFRONT_GROUP
     // (1, 4 or 8) and TWED_WAVEFRONT_SUB (in-group handoff rows: 8, 16 or 32)
     // override the choices for tuning runs.
     const int64_t cus = std::max(1, device_simds() / 4);
     w.group = 1;
     for (int G : {8, 4})
-        if (w.nStrips * 10 >= (int64_t)G * cus * 9) {
+        if (w.nStrips * 10 >= (int64_t)G * cus * 9 && wavefront_scratch_bytes(prec, cp, K, G) == 0) {
             w.group = G;
             break;
         }
@@ -397,7 +400,7 @@ twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA, const void
         if (wavefront_scratch_bytes(prec, cp, K, 1) != 0) continue;
         const int64_t strips = (nB + 64 * K - 1) / (64 * K);
         for (int G : {8, 4, 1}) {
-            if (G > 1 && strips < 2 * G) continue;
+            if (G > 1 && (strips < 2 * G || wavefront_scratch_bytes(prec, cp, K, G) != 0)) continue;
             const SweepChoice c{K, G, 4};
             // restaging A zeroes the flags and the ticket for this run
             e = launch_stage(prec, cp, A, TA, nullptr, 1, rows, rows, rows + 1, L.rowsA, flags, L.zero_words, st);

@@ -31,6 +31,7 @@ hipError_t by_dim(int dimt, int pm, Fn &&fn)
     case 4: return by_pm<CT, AT, 4>(pm, fn);
     case 8: return by_pm<CT, AT, 8>(pm, fn);
     case 16: return by_pm<CT, AT, 16>(pm, fn);
+    case 32: return by_pm<CT, AT, 32>(pm, fn);
     default: return hipErrorInvalidValue;
     }
 }

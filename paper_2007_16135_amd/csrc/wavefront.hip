@@ -412,14 +412,23 @@ hipError_t launch_offset(Prec prec, const CostParams &cp, const void *rowsA, int
     });
 }
 
+// Strip widths compiled for a sample dimension: beyond 16 components a lane
+// holds at most two columns (wider strips would not fit the register file).
+template <int DIMT, int K>
+constexpr bool kStripCompiled = DIMT <= 16 || K <= 2;
+
 hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, hipStream_t st)
 {
     return by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
         switch (K) {
         case 1: return launch_k<CT, AT, DIMT, PM, 1>(a, cp, st);
         case 2: return launch_k<CT, AT, DIMT, PM, 2>(a, cp, st);
-        case 4: return launch_k<CT, AT, DIMT, PM, 4>(a, cp, st);
-        case 8: return launch_k<CT, AT, DIMT, PM, 8>(a, cp, st);
+        case 4:
+            if constexpr (kStripCompiled<DIMT, 4>) return launch_k<CT, AT, DIMT, PM, 4>(a, cp, st);
+            return hipErrorInvalidValue;
+        case 8:
+            if constexpr (kStripCompiled<DIMT, 8>) return launch_k<CT, AT, DIMT, PM, 8>(a, cp, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
         }
     });
@@ -440,8 +449,12 @@ size_t wavefront_scratch_bytes(Prec prec, const CostParams &cp, int K, int G)
         switch (K) {
         case 1: bytes = pick.template operator()<1>(); break;
         case 2: bytes = pick.template operator()<2>(); break;
-        case 4: bytes = pick.template operator()<4>(); break;
-        case 8: bytes = pick.template operator()<8>(); break;
+        case 4:
+            if constexpr (kStripCompiled<DIMT, 4>) bytes = pick.template operator()<4>();
+            break;
+        case 8:
+            if constexpr (kStripCompiled<DIMT, 8>) bytes = pick.template operator()<8>();
+            break;
         default: break;
         }
         return hipSuccess;
@@ -456,8 +469,12 @@ int wavefront_max_workers(Prec prec, const CostParams &cp, int K, int G)
         switch (K) {
         case 1: per_cu = occupancy_k<CT, AT, DIMT, PM, 1>(G); break;
         case 2: per_cu = occupancy_k<CT, AT, DIMT, PM, 2>(G); break;
-        case 4: per_cu = occupancy_k<CT, AT, DIMT, PM, 4>(G); break;
-        case 8: per_cu = occupancy_k<CT, AT, DIMT, PM, 8>(G); break;
+        case 4:
+            if constexpr (kStripCompiled<DIMT, 4>) per_cu = occupancy_k<CT, AT, DIMT, PM, 4>(G);
+            break;
+        case 8:
+            if constexpr (kStripCompiled<DIMT, 8>) per_cu = occupancy_k<CT, AT, DIMT, PM, 8>(G);
+            break;
         default: break;
         }
         return hipSuccess;

@@ -156,6 +156,19 @@ def paper_shaped_collection(count: int, length: int, seed: int = 600) -> Collect
     return pack(xs, ts)
 
 
+def paper_shaped_rn(count: int = 60000, length: int = 28, dim: int = 28, seed: int = 28) -> Collection:
+    """Series of `length` samples in R^dim with regular timestamps -- the
+    shape of the paper's R^N timing (one query against 60,000 series of 28
+    steps in R^28), with seeded Gaussian random walks standing in for the
+    images (series k from default_rng([seed, k]))."""
+    xs, ts = [], []
+    for k in range(count):
+        r = np.random.default_rng([seed, k])
+        xs.append(walk(r, length, dim))
+        ts.append(regular_times(length))
+    return pack(xs, ts)
+
+
 # ---- learned k-NN workload ---------------------------------------------------
 
 N_CLASSES = 8

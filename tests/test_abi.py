@@ -69,7 +69,13 @@ def test_pair_argument_errors(L):
     for kw in [dict(nu=-1.0), dict(lam=-0.5), dict(p=0.5), dict(nu=float("nan")),
                dict(lam=float("inf")), dict(p=float("inf")), dict(dim=0)]:
         assert _pair(L, tw.make_params(**kw)) == INVALID, kw
-    assert _pair(L, tw.make_params(dim=17)) == UNSUPPORTED
+    assert _pair(L, tw.make_params(dim=33)) == UNSUPPORTED
+    assert _pair(L, tw.make_params(dim=20, strip_k=4)) == UNSUPPORTED
+    assert _pair(L, tw.make_params(dim=32, strip_k=8)) == UNSUPPORTED
+    # up to 32 components with strips of one or two columns: only the
+    # missing workspace is reported
+    for k in (0, 1, 2):
+        assert _pair(L, tw.make_params(dim=28, strip_k=k)) == WORKSPACE
     assert _pair(L, tw.make_params(precision=7)) == INVALID
     assert _pair(L, tw.make_params(algo=5)) == INVALID
     assert _pair(L, tw.make_params(strip_k=3)) == INVALID

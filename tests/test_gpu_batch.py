@@ -147,3 +147,21 @@ def test_all_pairs_2048_sampled():
     err = max_rel(D[prs[:, 0], prs[:, 1]], ref)
     say(f"max relative error of sampled entries: {err:.3e}")
     assert err <= 1e-5
+
+
+def test_paper_shaped_rn_query_vs_oracle():
+    """One query against many 28-step series in R^28 (the shape of the paper's
+    R^N experiment) in the rectangular batch mode, FP64, against the oracle."""
+    col = synth.paper_shaped_rn(count=300, length=28, dim=28, seed=29)
+    q = col.subset([0])
+    X, T = to_dev(q, "f64")
+    Y, TY = to_dev(col, "f64")
+    say("batch R^28 1 x 300 f64")
+    D = tw.twed_batch(X.reshape(-1, 28), T, q.off, Y.reshape(-1, 28), TY, col.off, nu=1e-3, lam=1.0, p=2.0,
+                      precision="f64")
+    torch.cuda.synchronize()
+    D = D.cpu().numpy().reshape(-1)
+    pairs = np.array([(0, j) for j in range(col.count)], dtype=np.int64)
+    ref = oracle.get().pairs(q.X, q.T, q.off, col.X, col.T, col.off, pairs, 1e-3, 1.0, 2.0, threads=8)
+    assert max_rel(D, ref) <= 1e-12
+    assert D[0] == 0.0

@@ -312,3 +312,47 @@ def test_tuner_picks_a_configuration_and_keeps_results():
     after = float(tw.twed_pair(A, TA, B, TB, c.nu, c.lam, c.p, "f64").item())
     tw.twed_tune_clear()
     assert after == before
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pair_replays_from_a_captured_graph(prec):
+    """twed_pair enqueues only kernels (staging also clears the flags and the
+    work ticket), so it can be captured in a graph: every replay, with other
+    library work and host synchronisation in between, gives the eager value."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    c = synth.random_pair(61, 62, 6000, 5000, 3, irregular=True, nu=0.01, lam=0.5, p=2.0)
+    other = synth.random_pair(63, 64, 900, 1100, 3, irregular=True, nu=0.01, lam=0.5, p=2.0)
+    A, TA, B, TB = dev(c.A, dt), dev(c.TA, dt), dev(c.B, dt), dev(c.TB, dt)
+    oA, oTA, oB, oTB = dev(other.A, dt), dev(other.TA, dt), dev(other.B, dt), dev(other.TB, dt)
+    prm = tw.make_params(c.nu, c.lam, c.p, 3, prec)
+    ws = torch.empty(tw.twed_pair_workspace_size(6000, 5000, prm), dtype=torch.uint8, device="cuda")
+    out = torch.empty(1, dtype=dt, device="cuda")
+    eager = float(tw.twed_pair(A, TA, B, TB, c.nu, c.lam, c.p, prec, out=out, workspace=ws).item())
+    other_eager = float(tw.twed_pair(oA, oTA, oB, oTB, other.nu, other.lam, other.p, prec).item())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say(f"graph capture {prec}")
+    with torch.cuda.graph(g):
+        tw.twed_pair(A, TA, B, TB, c.nu, c.lam, c.p, prec, out=out, workspace=ws)
+    for i in range(4):
+        out.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert float(out.item()) == eager, (i, float(out.item()), eager)
+        v = float(tw.twed_pair(oA, oTA, oB, oTB, other.nu, other.lam, other.p, prec).item())
+        assert v == other_eager
+
+
+@pytest.mark.parametrize("dim", [20, 28, 32])
+def test_high_dimensional_points_vs_oracle(dim):
+    """Samples of up to 32 components (the 32-component kernels, strips of at
+    most two columns per lane) against the FP64 oracle."""
+    c = synth.random_pair(70 + dim, 71 + dim, 300, 230, dim, irregular=True, nu=0.02, lam=0.7, p=2.0)
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5), ("f32_acc64", 1e-6)):
+        A, TA, B, TB = (c.A, c.TA, c.B, c.TB) if prec == "f64" else \
+            tuple(np.asarray(x, np.float32).astype(np.float64) for x in (c.A, c.TA, c.B, c.TB))
+        ref = oracle.twed(A, TA, B, TB, c.nu, c.lam, c.p)
+        for k in (0, 1, 2):
+            say(f"dim {dim} {prec} K={k}")
+            v = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec, strip_k=k)
+            assert abs(v - ref) <= tol * abs(ref), (dim, prec, k, v, ref)
