@@ -52,6 +52,10 @@ class Oracle:
                                           _i64_p, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           _dbl_p, ctypes.c_int32]
+        lib.twed_oracle_matrix_x.restype = ctypes.c_double
+        lib.twed_oracle_matrix_x.argtypes = lib.twed_oracle_matrix.argtypes + [_dbl_p]
+        lib.twed_oracle_path.restype = ctypes.c_int64
+        lib.twed_oracle_path.argtypes = lib.twed_oracle_matrix.argtypes[:-1] + [_i64_p]
         lib.twed_oracle_mutant.restype = ctypes.c_int32
         self.lib = lib
         self.mutant = lib.twed_oracle_mutant()
@@ -89,6 +93,39 @@ class Oracle:
             v = self.lib.twed_oracle_matrix(*args, DP.ctypes.data_as(_dbl_p))
             return v, DP
         return self.lib.twed_oracle_matrix(*args, None)
+
+    def _args(self, A, TA, B, TB, nu, lam, p):
+        A, B = self._pts(A), self._pts(B)
+        TA, TB = self._vec(TA), self._vec(TB)
+        nA, dim = A.shape
+        nB = B.shape[0]
+        if B.shape[1] != dim or TA.shape[0] != nA or TB.shape[0] != nB:
+            raise ValueError("shape mismatch")
+        keep = (A, TA, B, TB)
+        return keep, (A.ctypes.data_as(_dbl_p), TA.ctypes.data_as(_dbl_p), nA,
+                      B.ctypes.data_as(_dbl_p), TB.ctypes.data_as(_dbl_p), nB, dim,
+                      float(nu), float(lam), float(p))
+
+    def matrix_x(self, A, TA, B, TB, nu, lam, p=1.0):
+        """(DP, X): the full DP matrix and X = DP + e, both (nA+1, nB+1)."""
+        keep, args = self._args(A, TA, B, TB, nu, lam, p)
+        nA, nB = args[2], args[5]
+        DP = np.empty((nA + 1, nB + 1), dtype=np.float64)
+        X = np.empty_like(DP)
+        self.lib.twed_oracle_matrix_x(*args, DP.ctypes.data_as(_dbl_p), X.ctypes.data_as(_dbl_p))
+        return DP, X
+
+    def path(self, A, TA, B, TB, nu, lam, p=1.0):
+        """One optimal alignment path as an (L, 2) int64 array of cells (i, j)
+        from (0, 0) to (nA, nB); ties prefer the match, then the deletion in
+        A, then the deletion in B."""
+        keep, args = self._args(A, TA, B, TB, nu, lam, p)
+        nA, nB = args[2], args[5]
+        P = np.empty((nA + nB + 1, 2), dtype=np.int64)
+        n = self.lib.twed_oracle_path(*args, P.ctypes.data_as(_i64_p))
+        if n < 0:
+            raise ValueError("no finite path")
+        return P[:n].copy()
 
     def pairs(self, X, TX, offX, Y, TY, offY, pairs, nu, lam, p=1.0, threads=None):
         """TWED for explicit (i, j) pairs of two packed collections (CSR offsets)."""

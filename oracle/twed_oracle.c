@@ -277,6 +277,113 @@ double twed_oracle_rows(const double *A, const double *TA, int64_t nA,
     return r;
 }
 
+/* ---- band state and alignment path ----------------------------------------- */
+
+/*
+ * Point cost of cell (i, j): delta(A'_i, B'_j) + nu*|TA'_i - TB'_j|.  A match
+ * cost is the sum of two of them, mat(i, j) = e(i, j) + e(i-1, j-1) (up to
+ * the order of the additions).
+ */
+static double point_cost(int64_t i, int64_t j, const problem *pr)
+{
+    const int dim = pr->dim;
+    return point_dist(pr->Ap + i * dim, pr->Bp + j * dim, dim, pr->p) +
+           pr->nu * fabs(pr->TAp[i] - pr->TBp[j]);
+}
+
+/*
+ * The full DP matrix and, beside it, X[i][j] = DP[i][j] + e(i, j): the
+ * quantity a row of the band must carry so that the match into (i+1, j+1)
+ * can be formed from DP[i][j] without the samples of row i (the state that a
+ * sweep resumed below row i, or right of column j, starts from; section
+ * "Improved Time Warp Edit Distance", the band holds the whole state).
+ * DP and X are row-major with row stride nB+1.  Returns DP[nA][nB].
+ */
+double twed_oracle_matrix_x(const double *A, const double *TA, int64_t nA,
+                            const double *B, const double *TB, int64_t nB,
+                            int32_t dim, double nu, double lambda, double p,
+                            double *DP, double *X)
+{
+    if (nA < 1 || nB < 1 || dim < 1 || !DP || !X) return NAN;
+    double r = twed_oracle_matrix(A, TA, nA, B, TB, nB, dim, nu, lambda, p, DP);
+    problem pr;
+    double *bufs[4] = {0}, *delA = NULL, *delB = NULL;
+    if (setup(A, TA, nA, B, TB, nB, dim, nu, lambda, p, &pr, bufs, &delA, &delB)) {
+        release(bufs, delA, delB);
+        return NAN;
+    }
+    const int64_t W = nB + 1;
+    for (int64_t i = 0; i <= nA; i++)
+        for (int64_t j = 0; j <= nB; j++)
+            X[i * W + j] = DP[i * W + j] + point_cost(i, j, &pr);
+    release(bufs, delA, delB);
+    return r;
+}
+
+/*
+ * One optimal alignment path, read back from (nA, nB) to (0, 0) over the
+ * full matrix: at each cell the move whose candidate (the three terms of
+ * step 5) is the minimum, preferring the match, then the deletion in A (from
+ * the cell above), then the deletion in B (from the cell on the left).
+ * Writes the cells from (0, 0) to (nA, nB) as (i, j) pairs into path
+ * (capacity nA + nB + 1 pairs) and returns their number, or -1 if the path
+ * cannot be followed (non-finite distance, allocation failure).
+ */
+int64_t twed_oracle_path(const double *A, const double *TA, int64_t nA,
+                         const double *B, const double *TB, int64_t nB,
+                         int32_t dim, double nu, double lambda, double p,
+                         int64_t *path)
+{
+    if (nA < 1 || nB < 1 || dim < 1 || !path) return -1;
+    const int64_t W = nB + 1;
+    double *M = (double *)malloc((size_t)(nA + 1) * (size_t)W * sizeof(double));
+    if (!M) return -1;
+    double r = twed_oracle_matrix(A, TA, nA, B, TB, nB, dim, nu, lambda, p, M);
+    problem pr;
+    double *bufs[4] = {0}, *delA = NULL, *delB = NULL;
+    if (!isfinite(r) || setup(A, TA, nA, B, TB, nB, dim, nu, lambda, p, &pr, bufs, &delA, &delB)) {
+        release(bufs, delA, delB);
+        free(M);
+        return -1;
+    }
+    int64_t i = nA, j = nB, n = 0;
+    const int64_t cap = nA + nB + 1;
+    for (;;) {
+        path[2 * n] = i;
+        path[2 * n + 1] = j;
+        n++;
+        if (i == 0 && j == 0) break;
+        if (i == 0 || j == 0 || n >= cap) {
+            n = -1;
+            break;
+        }
+        const double cm = M[(i - 1) * W + j - 1] + mat_cost(i, j, &pr);
+        const double cu = M[(i - 1) * W + j] + delA[i];
+        const double cl = M[i * W + j - 1] + delB[j];
+        if (cm <= cu && cm <= cl) {
+            i--;
+            j--;
+        } else if (cu <= cl) {
+            i--;
+        } else {
+            j--;
+        }
+    }
+    if (n > 0) {
+        /* reverse into (0, 0) .. (nA, nB) order */
+        for (int64_t a = 0, b = n - 1; a < b; a++, b--) {
+            int64_t ti = path[2 * a], tj = path[2 * a + 1];
+            path[2 * a] = path[2 * b];
+            path[2 * a + 1] = path[2 * b + 1];
+            path[2 * b] = ti;
+            path[2 * b + 1] = tj;
+        }
+    }
+    release(bufs, delA, delB);
+    free(M);
+    return n;
+}
+
 /* ---- batches: independent pairs spread over threads ---------------------- */
 
 typedef struct {

@@ -15,6 +15,12 @@ Pins:
   time rescale     (T*s, nu/s) leaves D unchanged for s = 2^k
   1-D p-free       in one dimension every Lp distance is |x - y|
   prefix           DP[i][j] equals the distance of the prefixes A[:i], B[:j]
+  band state       X = DP + e against hand-worked e (tests/golden) and the
+                   brute force's own point cost
+  path             hand-worked paths; on integer data (exact sums) the path
+                   is, among all optimal brute-force paths, the one the tie
+                   rule selects (read back from the end: match, then
+                   deletion in A, then deletion in B)
 """
 from __future__ import annotations
 
@@ -90,6 +96,73 @@ def brute_force(A, TA, B, TB, nu, lam, p):
 
     walk(0, 0, 0.0)
     return best
+
+
+def _steps(A, TA, B, TB, nu, lam, p):
+    """The brute force's step costs and point cost as closures."""
+    Ap, TAp = _padded(A, TA)
+    Bp, TBp = _padded(B, TB)
+
+    def dA(i):
+        return _lp(Ap[i], Ap[i - 1], p) + nu * abs(TAp[i] - TAp[i - 1]) + lam
+
+    def dB(j):
+        return _lp(Bp[j], Bp[j - 1], p) + nu * abs(TBp[j] - TBp[j - 1]) + lam
+
+    def m(i, j):
+        return (_lp(Ap[i], Bp[j], p) + _lp(Ap[i - 1], Bp[j - 1], p)
+                + nu * (abs(TAp[i] - TBp[j]) + abs(TAp[i - 1] - TBp[j - 1])))
+
+    def e(i, j):
+        return _lp(Ap[i], Bp[j], p) + nu * abs(TAp[i] - TBp[j])
+
+    return len(Ap) - 1, len(Bp) - 1, dA, dB, m, e
+
+
+MATCH, UP, LEFT = 0, 1, 2
+
+
+def brute_force_paths(A, TA, B, TB, nu, lam, p):
+    """Every admissible path as (cost, moves), moves in forward order
+    (MATCH: (1,1), UP: (1,0) deletion in A, LEFT: (0,1) deletion in B)."""
+    nA, nB, dA, dB, m, _ = _steps(A, TA, B, TB, nu, lam, p)
+    out = []
+
+    def walk(i, j, acc, moves):
+        if i == nA and j == nB:
+            out.append((acc, tuple(moves)))
+            return
+        if i < nA and j < nB:
+            walk(i + 1, j + 1, acc + m(i + 1, j + 1), moves + [MATCH])
+        if i >= 1 and j >= 1:
+            if i < nA:
+                walk(i + 1, j, acc + dA(i + 1), moves + [UP])
+            if j < nB:
+                walk(i, j + 1, acc + dB(j + 1), moves + [LEFT])
+
+    walk(0, 0, 0.0, [])
+    return out
+
+
+def cells_of(moves):
+    i = j = 0
+    cells = [(0, 0)]
+    for mv in moves:
+        i += mv != LEFT
+        j += mv != UP
+        cells.append((i, j))
+    return cells
+
+
+def tie_rule_path(A, TA, B, TB, nu, lam, p):
+    """(cost, cells, number of optimal paths): the optimal path that the
+    backward reading picks when it prefers MATCH, then UP, then LEFT at every
+    cell, i.e. the optimal path whose reversed move list is smallest."""
+    paths = brute_force_paths(A, TA, B, TB, nu, lam, p)
+    best = min(c for c, _ in paths)
+    opt = [mv for c, mv in paths if c == best]
+    pick = min(opt, key=lambda mv: tuple(reversed(mv)))
+    return best, cells_of(pick), len(opt)
 
 
 def delannoy(m, n):
@@ -300,6 +373,75 @@ def check_prefix(orc, n_cases=6, seed=17):
     return fails
 
 
+def check_band_state(orc, n_cases=25, seed=18):
+    """X = DP + e: exact against the hand-worked e of the golden examples,
+    and within rounding of the brute force's own point cost on random data."""
+    fails = []
+    for c in load_worked_examples():
+        if "e" not in c:
+            continue
+        A = np.array(c["A"], float).reshape(-1, c["dim"])
+        B = np.array(c["B"], float).reshape(-1, c["dim"])
+        DP, X = orc.matrix_x(A, c["TA"], B, c["TB"], c["nu"], c["lambda"], c["p"])
+        want = np.array([[_inf(x) for x in row] for row in c["DP"]], float) + np.array(c["e"], float)
+        if not np.array_equal(X, want):
+            fails.append(f"{c['name']}: X {X.tolist()} != DP + e {want.tolist()}")
+    rng = np.random.default_rng(seed)
+    for _ in range(n_cases):
+        nA, nB = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        dim = int(rng.integers(1, 4))
+        p = float(rng.choice([1.0, 2.0, 3.0]))
+        nu = float(rng.choice([0.0, 0.05, 1.0]))
+        A, TA = rand_series(rng, nA, dim)
+        B, TB = rand_series(rng, nB, dim)
+        DP, X = orc.matrix_x(A, TA, B, TB, nu, 0.5, p)
+        _, _, _, _, _, e = _steps(A, TA, B, TB, nu, 0.5, p)
+        for i in range(nA + 1):
+            for j in range(nB + 1):
+                w = DP[i, j] + e(i, j)
+                if not (X[i, j] == w or abs(X[i, j] - w) <= 1e-13 * abs(w)):
+                    fails.append(f"X[{i},{j}] {X[i, j]!r} vs DP + e {w!r}")
+    return fails
+
+
+def check_paths(orc, n_cases=80, seed=19, max_n=6):
+    """Hand-worked paths, then the tie rule on integer data against the
+    brute force (every path sum is exact, so ties are real ties)."""
+    fails = []
+    for c in load_worked_examples():
+        if "path" not in c:
+            continue
+        A = np.array(c["A"], float).reshape(-1, c["dim"])
+        B = np.array(c["B"], float).reshape(-1, c["dim"])
+        P = orc.path(A, c["TA"], B, c["TB"], c["nu"], c["lambda"], c["p"])
+        if P.tolist() != c["path"]:
+            fails.append(f"{c['name']}: path {P.tolist()} != {c['path']}")
+    rng = np.random.default_rng(seed)
+    ties = 0
+    for _ in range(n_cases):
+        nA, nB = int(rng.integers(1, max_n + 1)), int(rng.integers(1, max_n + 1))
+        A = rng.integers(-3, 4, (nA, 1)).astype(float)
+        B = rng.integers(-3, 4, (nB, 1)).astype(float)
+        TA = np.cumsum(rng.integers(0, 3, nA)).astype(float)
+        TB = np.cumsum(rng.integers(0, 3, nB)).astype(float)
+        nu = float(rng.choice([0.0, 1.0, 2.0]))
+        lam = float(rng.choice([0.0, 1.0, 3.0]))
+        cost, cells, n_opt = tie_rule_path(A, TA, B, TB, nu, lam, 1.0)
+        ties += n_opt > 1
+        try:
+            P = orc.path(A, TA, B, TB, nu, lam, 1.0)
+        except ValueError:
+            fails.append(f"path {nA}x{nB}: no path")
+            continue
+        if [tuple(r) for r in P.tolist()] != cells:
+            fails.append(f"path {nA}x{nB} nu{nu} lam{lam}: {P.tolist()} vs tie rule {cells}")
+        if orc.twed(A, TA, B, TB, nu, lam, 1.0) != cost:
+            fails.append(f"path {nA}x{nB}: value vs brute force {cost}")
+    if ties < 10:
+        fails.append(f"only {ties} cases with tied optimal paths: the tie rule is not exercised")
+    return fails
+
+
 ALL_CHECKS = [check_worked_examples, check_brute_force, check_closed_form_single,
               check_metric_axioms, check_large_lambda, check_homogeneity,
-              check_p_free_1d, check_prefix]
+              check_p_free_1d, check_prefix, check_band_state, check_paths]
