@@ -56,6 +56,8 @@ class Oracle:
         lib.twed_oracle_matrix_x.argtypes = lib.twed_oracle_matrix.argtypes + [_dbl_p]
         lib.twed_oracle_path.restype = ctypes.c_int64
         lib.twed_oracle_path.argtypes = lib.twed_oracle_matrix.argtypes[:-1] + [_i64_p]
+        lib.twed_oracle_path_cost.restype = ctypes.c_double
+        lib.twed_oracle_path_cost.argtypes = lib.twed_oracle_matrix.argtypes[:-1] + [_i64_p, ctypes.c_int64]
         lib.twed_oracle_mutant.restype = ctypes.c_int32
         self.lib = lib
         self.mutant = lib.twed_oracle_mutant()
@@ -126,6 +128,13 @@ class Oracle:
         if n < 0:
             raise ValueError("no finite path")
         return P[:n].copy()
+
+    def path_cost(self, A, TA, B, TB, nu, lam, p, path):
+        """Summed step costs of a path ((L, 2) cells from (0, 0) to (nA, nB));
+        NaN if it is not an admissible path."""
+        keep, args = self._args(A, TA, B, TB, nu, lam, p)
+        P = np.ascontiguousarray(np.asarray(path, dtype=np.int64).reshape(-1, 2))
+        return self.lib.twed_oracle_path_cost(*args, P.ctypes.data_as(_i64_p), P.shape[0])
 
     def pairs(self, X, TX, offX, Y, TY, offY, pairs, nu, lam, p=1.0, threads=None):
         """TWED for explicit (i, j) pairs of two packed collections (CSR offsets)."""

@@ -384,6 +384,40 @@ int64_t twed_oracle_path(const double *A, const double *TA, int64_t nA,
     return n;
 }
 
+/*
+ * Cost of a given path: the sum, from (0, 0) forwards, of the cost of each
+ * step (mat(i, j) into (i, j) for a diagonal step, del_A(i) for a step down,
+ * del_B(j) for a step right).  Returns NAN if the cells do not form an
+ * admissible path from (0, 0) to (nA, nB) (steps other than those three, or
+ * a cell on row 0 / column 0 other than (0, 0)).
+ */
+double twed_oracle_path_cost(const double *A, const double *TA, int64_t nA,
+                             const double *B, const double *TB, int64_t nB,
+                             int32_t dim, double nu, double lambda, double p,
+                             const int64_t *path, int64_t len)
+{
+    if (nA < 1 || nB < 1 || dim < 1 || !path || len < 2) return NAN;
+    problem pr;
+    double *bufs[4] = {0}, *delA = NULL, *delB = NULL;
+    if (setup(A, TA, nA, B, TB, nB, dim, nu, lambda, p, &pr, bufs, &delA, &delB)) {
+        release(bufs, delA, delB);
+        return NAN;
+    }
+    double cost = 0.0;
+    int ok = path[0] == 0 && path[1] == 0 && path[2 * (len - 1)] == nA && path[2 * (len - 1) + 1] == nB;
+    for (int64_t k = 1; ok && k < len; k++) {
+        const int64_t i0 = path[2 * (k - 1)], j0 = path[2 * (k - 1) + 1];
+        const int64_t i = path[2 * k], j = path[2 * k + 1];
+        if (i < 1 || j < 1 || i > nA || j > nB) ok = 0;
+        else if (i == i0 + 1 && j == j0 + 1) cost = cost + mat_cost(i, j, &pr);
+        else if (i == i0 + 1 && j == j0) cost = cost + delA[i];
+        else if (i == i0 && j == j0 + 1) cost = cost + delB[j];
+        else ok = 0;
+    }
+    release(bufs, delA, delB);
+    return ok ? cost : NAN;
+}
+
 /* ---- batches: independent pairs spread over threads ---------------------- */
 
 typedef struct {

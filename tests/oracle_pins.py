@@ -428,6 +428,12 @@ def check_paths(orc, n_cases=80, seed=19, max_n=6):
         lam = float(rng.choice([0.0, 1.0, 3.0]))
         cost, cells, n_opt = tie_rule_path(A, TA, B, TB, nu, lam, 1.0)
         ties += n_opt > 1
+        # the cost of every admissible path against the brute force's sum
+        for c_bf, mv in brute_force_paths(A, TA, B, TB, nu, lam, 1.0)[:40]:
+            pc = orc.path_cost(A, TA, B, TB, nu, lam, 1.0, cells_of(mv))
+            if pc != c_bf:
+                fails.append(f"path cost {pc!r} vs brute force {c_bf!r}")
+                break
         try:
             P = orc.path(A, TA, B, TB, nu, lam, 1.0)
         except ValueError:
@@ -437,6 +443,19 @@ def check_paths(orc, n_cases=80, seed=19, max_n=6):
             fails.append(f"path {nA}x{nB} nu{nu} lam{lam}: {P.tolist()} vs tie rule {cells}")
         if orc.twed(A, TA, B, TB, nu, lam, 1.0) != cost:
             fails.append(f"path {nA}x{nB}: value vs brute force {cost}")
+    # real-valued data: the optimal path's cost is the distance, bit for bit
+    # (the DP sums the same steps in the same order); a non-path is rejected
+    for _ in range(15):
+        nA, nB = int(rng.integers(1, 30)), int(rng.integers(1, 30))
+        A, TA = rand_series(rng, nA, 2)
+        B, TB = rand_series(rng, nB, 2)
+        P = orc.path(A, TA, B, TB, 0.3, 0.7, 2.0)
+        if orc.path_cost(A, TA, B, TB, 0.3, 0.7, 2.0, P) != orc.twed(A, TA, B, TB, 0.3, 0.7, 2.0):
+            fails.append(f"path cost of the optimal path differs from the distance ({nA}x{nB})")
+        bad = P.copy()
+        bad[-1] = (nA + 1, nB)
+        if not math.isnan(orc.path_cost(A, TA, B, TB, 0.3, 0.7, 2.0, bad)):
+            fails.append("an inadmissible path was given a cost")
     if ties < 10:
         fails.append(f"only {ties} cases with tied optimal paths: the tie rule is not exercised")
     return fails
