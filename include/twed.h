@@ -142,6 +142,67 @@ twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA,
 /* Empties the tuning cache. */
 void twed_tune_clear(void);
 
+/* ---- blocks of the DP matrix (section "Improved Time Warp Edit Distance":
+ * the band of live cells is the whole state of the program, so a sweep can
+ * stop at any row or column and resume from it) ------------------------------
+ * A cell of the state: dp = DP(i, j) and x = DP(i, j) + e(i, j), where
+ * e(i, j) = d(A'_i, B'_j) + nu*|TA'_i - TB'_j| (padded samples as in
+ * twed_pair), the half of a match cost that the match into (i+1, j+1) takes
+ * from row i.  Row 0 and column 0 are the pad: DP(0, 0) = 0, X(0, 0) = 0 and
+ * +inf elsewhere on them. */
+typedef struct {
+    double dp;
+    double x;
+} twed_cell;
+
+/* Sweeps the block of rows r0+1..r1 and columns c0+1..c1 of the DP matrix of
+ * (A, B) (0 <= r0 < r1 <= nA, 0 <= c0 < c1 <= nB) from its top row and left
+ * column, exactly as twed_pair sweeps those cells: tiles swept in dependency
+ * order give the twed_pair value bitwise.  A, TA, B, TB are the whole series
+ * (device, as twed_pair); the block reads samples r0..r1 and c0..c1.
+ * top: device, c1-c0+1 cells of row r0 (columns c0..c1); NULL is the pad row
+ *   and is allowed only for r0 == 0.
+ * left: device, r1-r0+1 cells of column c0 (rows r0..r1); NULL is the pad
+ *   column, only for c0 == 0.  When both are given, top[0] is the corner.
+ * bottom (c1-c0+1 cells of row r1), right (r1-r0+1 cells of column c1) and
+ *   corner (one double, DP(r1, c1)): device outputs, each may be NULL.
+ * The caller owns every buffer.  Precision TWED_F64 or TWED_F32_ACC64
+ * (FP64 cells); strip_k as for twed_pair.
+ * Errors: as twed_pair, plus TWED_ERR_INVALID for a block outside the matrix
+ * or a missing top row / left column, TWED_ERR_UNSUPPORTED for another
+ * precision, TWED_ERR_WORKSPACE if ws_bytes <
+ * twed_pair_tile_workspace_size(r1 - r0, c1 - c0, prm). */
+size_t twed_pair_tile_workspace_size(int64_t rows, int64_t cols, const twed_params *prm);
+
+twed_status twed_pair_tile(const void *A, const void *TA, int64_t nA,
+                           const void *B, const void *TB, int64_t nB,
+                           const twed_params *prm, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                           const twed_cell *top, const twed_cell *left,
+                           twed_cell *bottom, twed_cell *right, double *corner,
+                           void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* One optimal alignment path of (A, B) (section "Time Warp Edit Distance":
+ * the path follows by backtracking over the choices of the forward problem).
+ * The cells (i, j) from (0, 0) to (nA, nB) go to `path` (device, capacity
+ * 2*(nA + nB + 1) int64, i and j interleaved) and their number to *path_len
+ * (device int64); out (device double) receives the distance.  Read back from
+ * (nA, nB), each cell is left by the move whose candidate is the minimum,
+ * preferring the match, then the deletion in A (from the cell above), then
+ * the deletion in B.  Memory: one forward sweep keeps every `block`-th row
+ * and (rounded up to the strip width) column; each block the path crosses
+ * is swept again recording one byte per cell; block == 0 means 4096.
+ * Precision TWED_F64 or TWED_F32_ACC64.  The call reads the walk's position
+ * between blocks, so it synchronises `stream` and returns when the path is
+ * complete.  Errors as twed_pair_tile, plus TWED_ERR_INVALID for NULL
+ * outputs or block < 0, and TWED_ERR_DEVICE when no finite path exists. */
+size_t twed_pair_path_workspace_size(int64_t nA, int64_t nB, const twed_params *prm, int64_t block);
+
+twed_status twed_pair_path(const void *A, const void *TA, int64_t nA,
+                           const void *B, const void *TB, int64_t nB,
+                           const twed_params *prm, int64_t block,
+                           double *out, int64_t *path, int64_t *path_len,
+                           void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* ---- many pairs (the paper's batch mode, section "cuTWED Implementation
  * Remarks"; the symmetric case computes only the upper triangle, as the
  * section "Validation using Real Datasets" anticipates) ---------------------

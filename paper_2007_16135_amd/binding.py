@@ -24,6 +24,7 @@ EXPORTS = [
     "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
     "twed_pair_tune", "twed_tune_clear",
+    "twed_pair_tile_workspace_size", "twed_pair_tile", "twed_pair_path_workspace_size", "twed_pair_path",
     "twed_embed_param_count", "twed_embed_max_length", "twed_embed_workspace_size", "twed_embed_forward",
     "twed_embed_loss_grad", "twed_embed_adamw", "twed_knn_index_storage_size", "twed_knn_index_create",
     "twed_knn_index_build_workspace_size", "twed_knn_index_build", "twed_knn_workspace_size", "twed_knn",
@@ -77,6 +78,16 @@ def load_library(path: str = LIB_PATH):
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.twed_pair_tune.restype = ctypes.c_int
     L.twed_tune_clear.argtypes = []
+    L.twed_pair_tile_workspace_size.argtypes = [_i64, _i64, _pp]
+    L.twed_pair_tile_workspace_size.restype = ctypes.c_size_t
+    L.twed_pair_tile.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, ctypes.c_size_t, _vp]
+    L.twed_pair_tile.restype = ctypes.c_int
+    L.twed_pair_path_workspace_size.argtypes = [_i64, _i64, _pp, _i64]
+    L.twed_pair_path_workspace_size.restype = ctypes.c_size_t
+    L.twed_pair_path.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                 _vp]
+    L.twed_pair_path.restype = ctypes.c_int
     L.twed_tune_clear.restype = None
     L.twed_batch_max_short_length.argtypes = [ctypes.c_int32]
     L.twed_batch_max_short_length.restype = ctypes.c_int64
@@ -207,6 +218,70 @@ def twed_pair(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", algo="auto
     _check(L.twed_pair(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
                        ctypes.byref(prm), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
     return out
+
+
+def _pair_operands(A, TA, B, TB, precision):
+    dt = input_dtype(precision)
+    A2 = A if A.dim() == 2 else A.reshape(-1, 1)
+    B2 = B if B.dim() == 2 else B.reshape(-1, 1)
+    _dev(A2, dt, "A"); _dev(B2, dt, "B"); _dev(TA, dt, "TA"); _dev(TB, dt, "TB")
+    nA, dim = A2.shape
+    nB = B2.shape[0]
+    if B2.shape[1] != dim or TA.numel() != nA or TB.numel() != nB:
+        raise ValueError("shape mismatch")
+    return A2, B2, nA, nB, dim
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def twed_pair_tile(A, TA, B, TB, r0, r1, c0, c1, top=None, left=None, nu=1e-3, lam=1.0, p=1.0,
+                   precision="f64", strip_k=0, bottom=True, right=True, workspace=None, stream=None):
+    """Sweeps rows r0+1..r1, columns c0+1..c1 of the DP matrix of (A, B) from
+    its top row and left column: float64 device tensors of (DP, X) cells,
+    shapes (c1-c0+1, 2) and (r1-r0+1, 2), None for the pad row / column.
+    Returns (corner, bottom, right): DP(r1, c1) as a one-element tensor and
+    the (DP, X) cells of row r1 and column c1 (None where not asked for)."""
+    torch = _torch()
+    A2, B2, nA, nB, dim = _pair_operands(A, TA, B, TB, precision)
+    for t, name, n in ((top, "top", c1 - c0 + 1), (left, "left", r1 - r0 + 1)):
+        if t is not None:
+            _dev(t, torch.float64, name)
+            if tuple(t.shape) != (n, 2):
+                raise ValueError(f"{name} must have shape ({n}, 2)")
+    prm = make_params(nu, lam, p, dim, precision, "auto", strip_k)
+    L = load_library()
+    ws = _workspace(L.twed_pair_tile_workspace_size(int(r1 - r0), int(c1 - c0), ctypes.byref(prm)), A2.device,
+                    workspace)
+    dev = A2.device
+    corner = torch.empty(1, dtype=torch.float64, device=dev)
+    bot = torch.empty((c1 - c0 + 1, 2), dtype=torch.float64, device=dev) if bottom else None
+    rig = torch.empty((r1 - r0 + 1, 2), dtype=torch.float64, device=dev) if right else None
+    _check(L.twed_pair_tile(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
+                            ctypes.byref(prm), int(r0), int(r1), int(c0), int(c1), _ptr(top), _ptr(left),
+                            _ptr(bot), _ptr(rig), corner.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return corner, bot, rig
+
+
+def twed_pair_path(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", block=0, strip_k=0,
+                   workspace=None, stream=None):
+    """(distance, path): a one-element float64 tensor and an (L, 2) int64
+    device tensor of the cells (i, j) of one optimal alignment path from
+    (0, 0) to (nA, nB).  Synchronises the stream."""
+    torch = _torch()
+    A2, B2, nA, nB, dim = _pair_operands(A, TA, B, TB, precision)
+    prm = make_params(nu, lam, p, dim, precision, "auto", strip_k)
+    L = load_library()
+    ws = _workspace(L.twed_pair_path_workspace_size(nA, nB, ctypes.byref(prm), int(block)), A2.device, workspace)
+    dev = A2.device
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    path = torch.empty((nA + nB + 1, 2), dtype=torch.int64, device=dev)
+    n = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(L.twed_pair_path(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
+                            ctypes.byref(prm), int(block), out.data_ptr(), path.data_ptr(), n.data_ptr(),
+                            ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out, path[: int(n.item())]
 
 
 def twed_pair_matrix(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", algo="auto", strip_k=0,

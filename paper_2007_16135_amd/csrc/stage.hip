@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void stage_kernel(const CT *__restrict__ X, co
                                                     const int64_t *__restrict__ off, int64_t nSeries,
                                                     int64_t n_single, int dim, CostArgs<CT> ca,
                                                     CT *__restrict__ rows, uint32_t *zero_ptr,
-                                                    int64_t zero_words, int64_t total_rows)
+                                                    int64_t zero_words, int64_t total_rows, int first_prev)
 {
     constexpr int S = Row<CT, DIMT>::kStride;
     const int64_t gtid = (int64_t)blockIdx.y * gridDim.x * blockDim.x + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,10 +55,10 @@ __global__ __launch_bounds__(256) void stage_kernel(const CT *__restrict__ X, co
 #pragma unroll
             for (int k = 0; k < DIMT; ++k) {
                 cur[k] = (r >= 1 && k < dim) ? X[(b + r - 1) * dim + k] : CT(0);
-                prev[k] = (r >= 2 && k < dim) ? X[(b + r - 2) * dim + k] : CT(0);
+                prev[k] = ((r >= 2 || (r == 1 && first_prev)) && k < dim) ? X[(b + r - 2) * dim + k] : CT(0);
             }
             const CT tc = r >= 1 ? T[b + r - 1] : CT(0);
-            const CT tp = r >= 2 ? T[b + r - 2] : CT(0);
+            const CT tp = (r >= 2 || (r == 1 && first_prev)) ? T[b + r - 2] : CT(0);
             CT del = CT(0);
             if (r >= 1) {
                 const CT d = point_dist<DIMT, PM, CT>(cur, prev, ca.p, ca.invp);
@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void stage_kernel(const CT *__restrict__ X, co
 
 hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const void *T,
                         const int64_t *off, int64_t nSeries, int64_t n_single, int64_t max_len,
-                        int64_t total_rows, void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st)
+                        int64_t total_rows, void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st,
+                        bool first_prev)
 {
     // Deletion costs are a cost term: computed in the cost precision.
     const Prec cprec = prec == kF64 ? kF64 : kF32;
@@ -93,7 +94,8 @@ hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const vo
         if (gy < 1) gy = 1;
         hipLaunchKernelGGL((stage_kernel<CT, DIMT, PM>), dim3(gx, gy), dim3(256), 0, st,
                            (const CT *)X, (const CT *)T, off, nSeries, n_single, cp.dim,
-                           CostArgs<CT>::make(cp), (CT *)rows, zero_ptr, zero_words, total_rows);
+                           CostArgs<CT>::make(cp), (CT *)rows, zero_ptr, zero_words, total_rows,
+                           first_prev ? 1 : 0);
         return hipGetLastError();
     });
 }

@@ -1,0 +1,306 @@
+// tile_capi.hip -- extern "C" entry points of the tile sweep and of the
+// alignment path (host code: argument checks, workspace layout, dispatch).
+//
+// A block of the DP matrix is swept from its top row and left column of
+// (DP, X = DP + e) cells (section "Improved Time Warp Edit Distance": the
+// band is the whole state), which gives resumable sweeps of long pairs and
+// the column shards a multi-GPU sweep would hand from GPU to GPU.  The path
+// is read back block by block from moves recorded during a second sweep of
+// each block the path crosses (section "Time Warp Edit Distance" names
+// backtracking over the forward problem's choices).
+#include "../../include/twed.h"
+#include "capi_util.h"
+#include "twed_kernels.h"
+
+#include <algorithm>
+#include <cstdint>
+
+using namespace twed;
+using namespace twed::capi;
+
+namespace {
+
+constexpr int64_t kTailWords = 4;      // work ticket, wait error word, two spare words
+constexpr size_t kDummyCells = 512;    // 64 lanes x up to 8 columns
+constexpr int64_t kDefaultBlock = 4096;
+constexpr size_t kCell = 16;           // one (DP, X) pair of FP64
+
+int simds()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
+    return cus * 4;
+}
+
+bool tile_prec(const twed_params *prm, Prec *out)
+{
+    if (prm->precision == TWED_F64) *out = kF64;
+    else if (prm->precision == TWED_F32_ACC64) *out = kF32Acc64;
+    else return false;
+    return true;
+}
+
+struct Sweep {
+    int K, G;
+};
+
+// The widest strip whose kernel keeps to registers and still leaves about
+// 1.5 strips per SIMD, in the widest non-spilling group that leaves about one
+// group per CU (the rules of the pair sweep).
+Sweep tile_sweep(int strip_k, int64_t nB, Prec prec, const CostParams &cp)
+{
+    int K = 1;
+    if (strip_k > 0) {
+        K = strip_k;
+    } else {
+        const int64_t want = (int64_t)simds() * 3 / 2;
+        for (int k : {8, 4, 2}) {
+            const int64_t strips = (nB + 64 * k - 1) / (64 * k);
+            if (strips >= want && tile_scratch_bytes(prec, cp, k, 1) == 0) {
+                K = k;
+                break;
+            }
+        }
+    }
+    const int64_t nStrips = (nB + 64 * K - 1) / (64 * K);
+    const int64_t cus = std::max(1, simds() / 4);
+    int G = 1;
+    for (int g : {8, 4})
+        if (nStrips * 10 >= (int64_t)g * cus * 9 && tile_scratch_bytes(prec, cp, K, g) == 0) {
+            G = g;
+            break;
+        }
+    return Sweep{K, G};
+}
+
+// Staged rows, handoff slots, flags and scratch of one sweep of nA x nB.
+struct SweepBuffers {
+    void *rowsA, *rowsB, *bnd, *dummy, *tmp;
+    uint32_t *flags;
+    int64_t zero_words;
+};
+
+void take_sweep(Carver &c, SweepBuffers &b, Prec prec, int dimt, int64_t nA, int64_t nB)
+{
+    b.rowsA = take_rows(c, prec, dimt, nA + 1);
+    b.rowsB = take_rows(c, prec, dimt, nB + 1);
+    b.bnd = c.take((size_t)2 * (size_t)(nA + 1) * kCell);
+    b.zero_words = (nB + 63) / 64 + kTailWords;
+    b.flags = (uint32_t *)c.take((size_t)b.zero_words * 4);
+    b.dummy = c.take(kDummyCells * kCell);
+    b.tmp = c.take(8);
+}
+
+twed_status run_tile(Prec prec, const CostParams &cp, Sweep sw, const void *rowsA, const void *rowsB, int64_t nA,
+                     int64_t nB, const SweepBuffers &b, const TileArgs &t, void *out, hipStream_t st)
+{
+    WavefrontArgs w{};
+    w.rowsA = rowsA;
+    w.rowsB = rowsB;
+    w.nA = nA;
+    w.nB = nB;
+    w.bnd = b.bnd;
+    w.flags = b.flags;
+    w.ticket = b.flags + (b.zero_words - kTailWords);
+    w.beta = w.ticket + 2;
+    w.nStrips = (nB + 64 * sw.K - 1) / (64 * sw.K);
+    w.out = out;
+    w.dump = nullptr;
+    w.group = sw.G;
+    w.sub_shift = 4;
+    const int workers = tile_max_workers(prec, cp, sw.K, sw.G);
+    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+    w.grid = (int)std::min<int64_t>((w.nStrips + sw.G - 1) / sw.G, workers);
+    const hipError_t e = launch_tile(prec, cp, sw.K, w, t, st);
+    if (e != hipSuccess) return fail_hip(e, "tile sweep launch");
+    return TWED_OK;
+}
+
+twed_status check_series(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB)
+{
+    if (!A || !TA || !B || !TB) return fail(TWED_ERR_INVALID, "NULL array argument");
+    if (nA < 1 || nB < 1) return fail(TWED_ERR_INVALID, "series lengths must be >= 1");
+    if (nA > kMaxLen || nB > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    return TWED_OK;
+}
+
+size_t row_bytes(Prec prec, int dimt) { return (size_t)row_stride(prec, dimt) * cost_size(prec); }
+
+// ---- path layout ---------------------------------------------------------------
+
+struct PathGeometry {
+    Sweep fwd, blk;
+    int64_t H, Wc, nr, nc;
+};
+
+PathGeometry path_geometry(const twed_params *prm, int64_t nA, int64_t nB, int64_t block, Prec prec,
+                           const CostParams &cp)
+{
+    PathGeometry g{};
+    const int64_t want = block > 0 ? block : kDefaultBlock;
+    g.fwd = tile_sweep(prm->strip_k, nB, prec, cp);
+    const int64_t W = 64 * (int64_t)g.fwd.K;
+    g.H = std::max<int64_t>(64, want);
+    g.Wc = (std::max(want, W) + W - 1) / W * W;
+    g.nr = (nA - 1) / g.H;
+    g.nc = (nB - 1) / g.Wc;
+    g.blk = tile_sweep(0, std::min(g.Wc, nB), prec, cp);
+    return g;
+}
+
+struct PathLayout {
+    SweepBuffers b;
+    void *ckrow, *ckcol, *dirs;
+    int64_t *st;
+    size_t total;
+};
+
+PathLayout path_layout(char *base, const twed_params *prm, int64_t nA, int64_t nB, const PathGeometry &g, Prec prec)
+{
+    Carver c{base};
+    PathLayout L{};
+    take_sweep(c, L.b, prec, dimt_for(prm->dim), nA, nB);
+    L.st = (int64_t *)c.take(4 * sizeof(int64_t));
+    L.ckrow = c.take((size_t)g.nr * (size_t)(nB + 1) * kCell);
+    L.ckcol = c.take((size_t)g.nc * (size_t)(nA + 1) * kCell);
+    const int64_t Wb = 64 * (int64_t)g.blk.K;
+    const int64_t strips = (std::min(g.Wc, nB) + Wb - 1) / Wb;
+    L.dirs = c.take((size_t)strips * (size_t)(std::min(g.H, nA) + 64) * (size_t)Wb);
+    L.total = c.used;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t twed_pair_tile_workspace_size(int64_t rows, int64_t cols, const twed_params *prm)
+{
+    Prec prec;
+    if (rows < 1 || cols < 1 || rows > kMaxLen || cols > kMaxLen) return 0;
+    if (check_params(prm) != TWED_OK || !tile_prec(prm, &prec)) return 0;
+    Carver c{nullptr};
+    SweepBuffers b{};
+    take_sweep(c, b, prec, dimt_for(prm->dim), rows, cols);
+    return c.used;
+}
+
+twed_status twed_pair_tile(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                           const twed_params *prm, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                           const twed_cell *top, const twed_cell *left, twed_cell *bottom, twed_cell *right,
+                           double *corner, void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    last_error().clear();
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    if ((s = check_series(A, TA, nA, B, TB, nB)) != TWED_OK) return s;
+    if (!(0 <= r0 && r0 < r1 && r1 <= nA && 0 <= c0 && c0 < c1 && c1 <= nB))
+        return fail(TWED_ERR_INVALID, "the block must satisfy 0 <= r0 < r1 <= nA and 0 <= c0 < c1 <= nB");
+    if (r0 > 0 && !top) return fail(TWED_ERR_INVALID, "a block below row 0 needs its top row");
+    if (c0 > 0 && !left) return fail(TWED_ERR_INVALID, "a block right of column 0 needs its left column");
+    Prec prec;
+    if (!tile_prec(prm, &prec)) return fail(TWED_ERR_UNSUPPORTED, "tiles take TWED_F64 or TWED_F32_ACC64");
+    const int64_t nAt = r1 - r0, nBt = c1 - c0;
+    const size_t need = twed_pair_tile_workspace_size(nAt, nBt, prm);
+    if ((s = check_workspace(workspace, ws_bytes, need)) != TWED_OK) return s;
+    Carver c{(char *)workspace};
+    SweepBuffers b{};
+    const int dimt = dimt_for(prm->dim);
+    take_sweep(c, b, prec, dimt, nAt, nBt);
+    const CostParams cp = cost_params(prm);
+    const size_t es = cost_size(prec) * (size_t)prm->dim, ts = cost_size(prec);
+    hipError_t e = launch_stage(prec, cp, (const char *)A + r0 * es, (const char *)TA + r0 * ts, nullptr, 1, nAt,
+                                nAt, nAt + 1, b.rowsA, b.flags, b.zero_words, st, r0 > 0);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    e = launch_stage(prec, cp, (const char *)B + c0 * es, (const char *)TB + c0 * ts, nullptr, 1, nBt, nBt, nBt + 1,
+                     b.rowsB, nullptr, 0, st, c0 > 0);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    TileArgs t{};
+    t.top = top;
+    t.left = left;
+    t.bottom = bottom;
+    t.right = right;
+    t.dummy = b.dummy;
+    return run_tile(prec, cp, tile_sweep(prm->strip_k, nBt, prec, cp), b.rowsA, b.rowsB, nAt, nBt, b, t,
+                    corner ? (void *)corner : b.tmp, st);
+}
+
+size_t twed_pair_path_workspace_size(int64_t nA, int64_t nB, const twed_params *prm, int64_t block)
+{
+    Prec prec;
+    if (nA < 1 || nB < 1 || nA > kMaxLen || nB > kMaxLen || block < 0) return 0;
+    if (check_params(prm) != TWED_OK || !tile_prec(prm, &prec)) return 0;
+    const CostParams cp = cost_params(prm);
+    const PathGeometry g = path_geometry(prm, nA, nB, block, prec, cp);
+    return path_layout(nullptr, prm, nA, nB, g, prec).total;
+}
+
+twed_status twed_pair_path(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                           const twed_params *prm, int64_t block, double *out, int64_t *path, int64_t *path_len,
+                           void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    last_error().clear();
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    if ((s = check_series(A, TA, nA, B, TB, nB)) != TWED_OK) return s;
+    if (!out || !path || !path_len) return fail(TWED_ERR_INVALID, "NULL output argument");
+    if (block < 0) return fail(TWED_ERR_INVALID, "block must be >= 0");
+    Prec prec;
+    if (!tile_prec(prm, &prec)) return fail(TWED_ERR_UNSUPPORTED, "the path takes TWED_F64 or TWED_F32_ACC64");
+    const CostParams cp = cost_params(prm);
+    const PathGeometry g = path_geometry(prm, nA, nB, block, prec, cp);
+    if (g.H > 0x40000000LL || g.Wc > 0x40000000LL) return fail(TWED_ERR_UNSUPPORTED, "block too large");
+    if ((s = check_workspace(workspace, ws_bytes, path_layout(nullptr, prm, nA, nB, g, prec).total)) != TWED_OK)
+        return s;
+    const PathLayout L = path_layout((char *)workspace, prm, nA, nB, g, prec);
+    const SweepBuffers &b = L.b;
+    hipError_t e;
+#define TRY(call, what)                                \
+    do {                                               \
+        e = (call);                                    \
+        if (e != hipSuccess) return fail_hip(e, what); \
+    } while (0)
+    // forward sweep of the whole pair, keeping checkpoint rows and columns
+    TRY(launch_stage(prec, cp, A, TA, nullptr, 1, nA, nA, nA + 1, b.rowsA, b.flags, b.zero_words, st), "staging");
+    TRY(launch_stage(prec, cp, B, TB, nullptr, 1, nB, nB, nB + 1, b.rowsB, nullptr, 0, st), "staging");
+    TileArgs t{};
+    t.dummy = b.dummy;
+    t.ckrow = g.nr > 0 ? L.ckrow : nullptr;
+    t.ckcol = g.nc > 0 ? L.ckcol : nullptr;
+    t.ck_rows = (int)g.H;
+    t.ck_cols = (int)g.Wc;
+    s = run_tile(prec, cp, g.fwd, b.rowsA, b.rowsB, nA, nB, b, t, out, st);
+    if (s != TWED_OK) return s;
+    // backwards, block by block: sweep the block again recording moves, walk it
+    const int64_t cap = nA + nB + 1;
+    TRY(launch_walk_init(L.st, nA, nB, st), "walk set-up");
+    const size_t rb = row_bytes(prec, dimt_for(prm->dim));
+    int64_t hst[4] = {0, 0, 0, 0};
+    const int64_t max_blocks = g.nr + g.nc + 3;
+    for (int64_t it = 0;; ++it) {
+        TRY(hipMemcpyAsync(hst, L.st, sizeof(hst), hipMemcpyDeviceToHost, st), "walk state read");
+        TRY(hipStreamSynchronize(st), "walk state read");
+        if (hst[3] == 1) break;
+        if (hst[3] != 0 || it > max_blocks || hst[0] < 1 || hst[1] < 1)
+            return fail(TWED_ERR_DEVICE, "the path could not be followed (non-finite distance or a timed-out sweep)");
+        const int64_t br = (hst[0] - 1) / g.H, bc = (hst[1] - 1) / g.Wc;
+        const int64_t r0 = br * g.H, r1 = std::min(r0 + g.H, nA);
+        const int64_t c0 = bc * g.Wc, c1 = std::min(c0 + g.Wc, nB);
+        TRY(launch_zero32(b.flags, b.zero_words, st), "flag reset");
+        TileArgs u{};
+        u.dummy = b.dummy;
+        u.top = br > 0 ? (const char *)L.ckrow + ((size_t)(br - 1) * (size_t)(nB + 1) + (size_t)c0) * kCell : nullptr;
+        u.left = bc > 0 ? (const char *)L.ckcol + ((size_t)(bc - 1) * (size_t)(nA + 1) + (size_t)r0) * kCell : nullptr;
+        u.dirs = (uint8_t *)L.dirs;
+        s = run_tile(prec, cp, g.blk, (const char *)b.rowsA + r0 * rb, (const char *)b.rowsB + c0 * rb, r1 - r0,
+                     c1 - c0, b, u, b.tmp, st);
+        if (s != TWED_OK) return s;
+        TRY(launch_walk((const uint8_t *)L.dirs, r0, c0, g.blk.K, (r1 - r0) + 64, L.st, path, cap, st), "walk");
+    }
+    TRY(launch_order(L.st, path, path_len, cap, st), "path order");
+#undef TRY
+    return TWED_OK;
+}
+
+}  // extern "C"

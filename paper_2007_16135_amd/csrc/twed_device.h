@@ -214,6 +214,34 @@ __device__ __forceinline__ void lane_row(Lane<CT, AT, DIMT, K> &L, const Row<CT,
     xlast = L.xp[K - 1];
 }
 
+// lane_row for unshifted accumulators, also returning the move into each of
+// the K cells as byte j of the result: 0 the match, 1 the deletion in A (from
+// the cell above), 2 the deletion in B (from the cell on the left), ties
+// resolved in that order.  The cell values are those of lane_row.
+template <typename CT, typename AT, int DIMT, int PM, int K>
+__device__ __forceinline__ uint64_t lane_row_dirs(Lane<CT, AT, DIMT, K> &L, const Row<CT, DIMT> &a, AT &left,
+                                                  AT diag, AT &xlast, CT nu, CT p, CT invp)
+{
+    static_assert(!kShifted<AT> && K <= 8, "moves are recorded for FP64 accumulators, K <= 8");
+    const AT dela = (AT)a.del;
+    uint64_t code = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const CT dist = point_dist<DIMT, PM, CT>(a.x, L.bx[j], p, invp);
+        const AT e = (AT)fma_(nu, fabs_(a.t - L.bt[j]), dist);
+        const AT m = diag + e, u = L.up[j] + dela, l = left + L.bdel[j];
+        const AT v = dmin(dmin(m, u), l);
+        const uint64_t mv = (m <= u && m <= l) ? 0u : (u <= l ? 1u : 2u);
+        code |= mv << (8 * j);
+        diag = L.xp[j];
+        L.xp[j] = v + e;
+        L.up[j] = v;
+        left = v;
+    }
+    xlast = L.xp[K - 1];
+    return code;
+}
+
 // ---- FP32 drift control --------------------------------------------------------
 //
 // Every monotone path from (0,0) to (nA,nB) crosses each of the nA + nB

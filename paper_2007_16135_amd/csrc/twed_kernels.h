@@ -38,10 +38,13 @@ inline size_t rows_bytes(Prec prec, int dimt, int64_t rows)
 // series of n samples.  Row block of series s starts at row off[s] + s.
 // `rows` points after the front padding of a buffer of total_rows rows
 // (rows_bytes); the padding rows are zeroed too.  Also zeroes `zero_words`
-// 32-bit words at `zero_ptr` (may be null).
+// 32-bit words at `zero_ptr` (may be null).  With first_prev (a single
+// series only) X and T start one sample into a longer series: the deletion
+// cost of row 1 is taken against the sample before X[0] instead of the pad.
 hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const void *T,
                         const int64_t *off, int64_t nSeries, int64_t n_single, int64_t max_len,
-                        int64_t total_rows, void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st);
+                        int64_t total_rows, void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st,
+                        bool first_prev = false);
 
 // Single pair, persistent wave pipeline over strips of 64*K columns.
 struct WavefrontArgs {
@@ -68,6 +71,39 @@ hipError_t launch_offset(Prec prec, const CostParams &cp, const void *rowsA, int
 int wavefront_max_workers(Prec prec, const CostParams &cp, int K, int G);
 // Per-lane scratch (register spill) bytes of one wavefront instantiation.
 size_t wavefront_scratch_bytes(Prec prec, const CostParams &cp, int K, int G);
+
+// Boundaries and extra outputs of a tile sweep (device pointers to (DP, X)
+// cell pairs of FP64; any may be null).  See TileIO in wavefront_impl.h.
+struct TileArgs {
+    const void *top;    // row 0 of the block, columns 0..nB (null: pad row)
+    const void *left;   // column 0 of the block, rows 0..nA (null: pad column)
+    void *bottom;       // row nA, columns 0..nB
+    void *right;        // column nB, rows 0..nA
+    void *ckrow;        // rows ck_rows, 2*ck_rows, ... < nA, nB + 1 cells each
+    void *ckcol;        // columns ck_cols, 2*ck_cols, ... < nB, nA + 1 cells each
+    void *dummy;        // 512 cells of scratch
+    uint8_t *dirs;      // moves, nStrips * (nA + 64) * 64 * K bytes
+    int ck_rows;        // >= 64
+    int ck_cols;        // a multiple of the strip width 64*K
+};
+// The tile sweep (FP64 accumulators: kF64 or kF32Acc64).  `a` as for the
+// pair sweep, with rowsA / rowsB at the rows of the block's row 0 / column 0.
+hipError_t launch_tile(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, const TileArgs &t,
+                       hipStream_t st);
+size_t tile_scratch_bytes(Prec prec, const CostParams &cp, int K, int G);
+int tile_max_workers(Prec prec, const CostParams &cp, int K, int G);
+
+// Path read-back (path.hip).  st holds {r, c, cells written, status}.
+hipError_t launch_walk_init(int64_t *st, int64_t nA, int64_t nB, hipStream_t s);
+// Follows the moves of the block whose row 0 / column 0 are global row r0 /
+// column c0 (dirs in the tile sweep's order with strip width 64*K and T =
+// block rows + 64 steps per strip) until the walk leaves the block.
+hipError_t launch_walk(const uint8_t *dirs, int64_t r0, int64_t c0, int K, int64_t T, int64_t *st, int64_t *rev,
+                       int64_t cap, hipStream_t s);
+// Zeroes n 32-bit words (a kernel, so that it can be captured in a graph).
+hipError_t launch_zero32(uint32_t *p, int64_t n, hipStream_t s);
+// Reverses the st[2] cells of `path` in place and writes the count to len.
+hipError_t launch_order(const int64_t *st, int64_t *path, int64_t *len, int64_t cap, hipStream_t s);
 
 // Fills row 0 and column 0 of a dump matrix (0 at the corner, +inf elsewhere).
 hipError_t launch_dump_border(Prec prec, void *dump, int64_t nA, int64_t nB, hipStream_t st);

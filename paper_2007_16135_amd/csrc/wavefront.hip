@@ -27,307 +27,9 @@
 // Memory stays O(nA + nB): packed inputs, two boundary columns, one flag per
 // strip.  Every cell is evaluated once, in the operation order of the lane
 // code, so the result does not depend on scheduling.
-#include "twed_dispatch.h"
+#include "wavefront_impl.h"
 
 namespace twed {
-
-// Polls of a predecessor's progress word before a wave gives up (tens of
-// seconds).
-constexpr uint32_t kMaxPolls = 1u << 23;
-
-template <typename AT>
-struct alignas(2 * sizeof(AT)) Pair2 {
-    AT dp;
-    AT x;
-};
-
-// Rows per global handoff (one window of the 64-lane boundary register).
-// Inside a workgroup the handoff comes every 1 << sub_shift steps (8, 16 or
-// 32; a kernel argument).
-constexpr int kWindow = 64;
-// Rows of one in-group boundary kept in LDS (power of two), plus one slot
-// that absorbs the writes of lanes without a row.
-constexpr int kRing = 128;
-
-template <typename AT, int G>
-struct GroupShared {
-    Pair2<AT> ring[G > 1 ? G - 1 : 1][kRing + 1];  // boundary of wave w, read by wave w+1
-    uint32_t prod[G];                              // rows of that boundary published
-    uint32_t cons[G];                              // rows of wave w's left boundary consumed
-    uint32_t ticket[G];                            // ticket value seen by each wave (wave 0's is the claim)
-};
-
-// DPP control "wave_shl:1": lane i receives lane i+1; lane 63 keeps `old`.
-constexpr int kDppWaveShl1 = 0x130;
-
-__device__ __forceinline__ float collect(float v_lane63, float col)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        __builtin_bit_cast(int, v_lane63), __builtin_bit_cast(int, col), kDppWaveShl1, 0xf, 0xf, false));
-}
-
-__device__ __forceinline__ double collect(double v_lane63, double col)
-{
-    uint64_t u = __builtin_bit_cast(uint64_t, col);
-    uint64_t o = __builtin_bit_cast(uint64_t, v_lane63);
-    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u,
-                                                        kDppWaveShl1, 0xf, 0xf, false);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
-                                                        kDppWaveShl1, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ uint32_t load_lds_progress(const uint32_t *p)
-{
-    return wave_uniform(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-}
-
-// Bounded wait until *p >= need (uniform across the wave).  A wave that gives
-// up marks the error word (the result strip then reports NaN) and carries
-// on, and once the word is set no wave waits any more, so every wave still
-// reaches the end of the grid after at most one time-out.
-template <bool LDS>
-__device__ __forceinline__ void wait_progress(const uint32_t *p, uint32_t need, uint32_t *err)
-{
-    uint32_t polls = 0;
-    while ((LDS ? load_lds_progress(p) : load_progress(p)) < need) {
-        if (load_progress(err) != 0u) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (++polls > kMaxPolls) {
-            __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
-    }
-}
-
-// One strip of 64*K columns swept by one wave.  Its left boundary (DP and X =
-// DP + e of column c0-1, per row) comes from the previous strip: through LDS
-// when that strip belongs to the same workgroup (handoff every kSub rows,
-// workgroup-scope release/acquire), through a global slot and flag
-// otherwise (every kWindow rows, agent scope).  Its right boundary goes the
-// same two ways to the next strip.
-//
-// rowsA points at row 0 of A and must stay readable from row -64 to row
-// nA + 64 (the staging pads the buffer): lanes that have not started yet, or
-// have finished, read rows outside 1..nA and compute values nobody uses, so
-// the row address needs no clamp.
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP>
-__device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g, int s, const CT *__restrict__ rowsA,
-                                            const CT *__restrict__ rowsB, int nA, int nB, const CostArgs<CT> &ca,
-                                            Pair2<AT> *bnd, uint32_t *flags, uint32_t *err, int nStrips, CT beta,
-                                            AT *out, AT *dump, int sub_shift)
-{
-    const int kSub = 1 << sub_shift;
-    constexpr int S = Row<CT, DIMT>::kStride;
-    constexpr int W = kWave * K;
-    const int lane = threadIdx.x & (kWave - 1);
-    const AT INF = pinf<AT>();
-    const CT *rowsA_lane = rowsA - (ptrdiff_t)lane * S;  // row t of this pointer = row t - lane of A
-
-    // ---- columns of this lane
-    const int c0 = 1 + s * W + lane * K;
-    Lane<CT, AT, DIMT, K> L;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        Row<CT, DIMT> b;
-        const int c = c0 + j <= nB ? c0 + j : nB;
-        load_row<CT, DIMT>(rowsB, c, b);
-#pragma unroll
-        for (int k = 0; k < DIMT; ++k) L.bx[j][k] = b.x[k];
-        L.bt[j] = b.t;
-        L.bdel[j] = kShifted<AT> ? (AT)(b.del - beta) : (AT)b.del;
-        L.up[j] = INF;   // DP(0, c)
-        L.xp[j] = INF;   // DP(0, c) + e(0, c)
-    }
-
-    const bool in_global = w == 0 && s > 0;
-    const bool in_lds = w > 0;
-    const bool has_out = s + 1 < nStrips;
-    const bool out_lds = has_out && w < G - 1;
-    const bool out_global = has_out && w == G - 1;
-    // global slots alternate between consecutive groups (see the header comment)
-    const Pair2<AT> *in_slot = bnd + (size_t)((g + 1) & 1) * (size_t)(nA + 1);
-    Pair2<AT> *out_slot = bnd + (size_t)(g & 1) * (size_t)(nA + 1);
-    const uint32_t *in_flag = flags + (g > 0 ? g - 1 : 0);
-    uint32_t *out_flag = flags + g;
-
-    const int last_strip = (nB - 1) / W;
-    const int qs = (nB - 1) - last_strip * W;
-    const int lstar = qs / K, jstar = qs - (qs / K) * K;
-    const bool result_strip = s == last_strip;
-
-    // Operands shifted in from lane l-1 after each step: sh_l is the left
-    // operand DP(r, c0-1) of the next step, sh_xo its up-left operand
-    // X(r-1, c0-1) = DP + e, and sh_x the X value that becomes sh_xo one
-    // step later.  Lane 0 takes them from the strip's left boundary
-    // instead: +inf on the pad row and column, except X(0, 0) = 0 (minus
-    // the offset) for the first strip.
-    AT sh_l = INF;
-    AT sh_x = (lane == 0 && s == 0) ? -(AT)beta : INF;
-    AT sh_xo = INF;
-
-    const int T = nA + kWave;  // lane 63 reaches row nA at step nA + 63
-    Row<CT, DIMT> cur, nxt;
-    load_row<CT, DIMT>(rowsA_lane, 0, cur);
-    // Left boundary of the current window of 64 steps: lane l holds row
-    // wb + 1 + l (DP in cdp, X in cx; two scalars, so that selecting a lane's
-    // new row stays in registers).
-    AT cdp = INF, cx = INF;
-    // Right-boundary collector: lane 63's (DP, X) of each step enters at
-    // lane 63 and moves down one lane per step, so after step t lane l holds
-    // row t - 126 + l of the boundary.
-    AT col_dp = INF, col_x = INF;
-
-    for (int t0 = 0; t0 < T; t0 += kSub) {
-        const int q = (t0 >> sub_shift) & ((kWindow >> sub_shift) - 1);  // sub-chunk within the window
-        const int wb = t0 - q * kSub;                          // window start
-        const int steps = T - t0 < kSub ? T - t0 : kSub;
-        if (in_global && q == 0) {
-            const uint32_t need = (uint32_t)(t0 + kWindow < nA ? t0 + kWindow : nA);
-            wait_progress<false>(in_flag, need, err);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int rr = t0 + 1 + lane < nA ? t0 + 1 + lane : nA;
-            const Pair2<AT> v = in_slot[rr];
-            cdp = v.dp;
-            cx = v.x;
-        }
-        if (in_lds) {
-            const uint32_t need = (uint32_t)(t0 + kSub < nA ? t0 + kSub : nA);
-            wait_progress<true>(&sh.prod[w - 1], need, err);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const int rr = wb + 1 + lane < nA ? wb + 1 + lane : nA;
-            const Pair2<AT> v = sh.ring[w > 0 ? w - 1 : 0][rr & (kRing - 1)];
-            const bool mine = (lane >> sub_shift) == q;  // lanes of this sub-chunk take their rows
-            cdp = mine ? v.dp : cdp;
-            cx = mine ? v.x : cx;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __hip_atomic_store(&sh.cons[w], need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-
-        // One step: sweep row t - lane with `use`, prefetch row t + 1 - lane
-        // into `fill`.  Steps alternate the two row buffers, so the
-        // prefetched row never has to be copied.
-        auto step = [&](int i, Row<CT, DIMT> &use, Row<CT, DIMT> &fill) {
-            const int t = t0 + i;
-            load_row<CT, DIMT>(rowsA_lane, t + 1, fill);
-
-            AT left = sh_l, xl;
-            lane_row<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p, ca.invp, beta);
-
-            if constexpr (DUMP) {
-                const int r = t - lane;
-                if (r >= 1 && r <= nA) {
-#pragma unroll
-                    for (int j = 0; j < K; ++j)
-                        if (c0 + j <= nB)
-                            dump[(size_t)r * (size_t)(nB + 1) + (size_t)(c0 + j)] =
-                                kShifted<AT> ? (AT)((double)L.up[j] + (double)beta * (double)(r + c0 + j))
-                                             : L.up[j];
-                }
-            }
-            // The result is wave-uniform; every lane stores it (one
-            // transaction): no lane-conditional branch in the step loop.
-            if (result_strip && t == nA + lstar) {
-                AT res = L.up[0];
-#pragma unroll
-                for (int j = 1; j < K; ++j)
-                    if (j == jstar) res = L.up[j];
-                res = lane_value(res, lstar);
-                if (kShifted<AT>) res = (AT)((double)res + (double)beta * (double)(nA + nB));
-                if (load_progress(err) != 0u) res = __builtin_nan("");
-                out[0] = res;
-            }
-
-            const bool has_in = in_global || in_lds;
-            const AT bl = has_in ? lane_value(cdp, t - wb) : INF;
-            const AT bx = has_in ? lane_value(cx, t - wb) : INF;
-            sh_xo = sh_x;
-            sh_l = shift_in(left, bl);
-            sh_x = shift_in(xl, bx);
-            if (has_out) {
-                col_dp = collect(left, col_dp);
-                col_x = collect(xl, col_x);
-            }
-        };
-        int i = 0;
-        for (; i + 1 < steps; i += 2) {
-            step(i, cur, nxt);
-            step(i + 1, nxt, cur);
-        }
-        if (i < steps) {
-            step(i, cur, nxt);
-            cur = nxt;
-        }
-
-        const int tend = t0 + steps;        // steps done so far
-        const int last = tend - kWave;      // last boundary row complete
-        if (out_lds && last >= 1) {
-            // the ring holds rows last-kRing+1 .. last: the consumer must be
-            // past the rows being overwritten
-            if (last > kRing) wait_progress<true>(&sh.cons[w + 1], (uint32_t)(last - kRing), err);
-            int r = tend - 2 * kWave + 1 + lane;  // row held by this lane
-            const bool mine = lane >= kWave - steps && r >= 1 && r <= nA;
-            sh.ring[w < G - 1 ? w : 0][mine ? (r & (kRing - 1)) : kRing] = Pair2<AT>{col_dp, col_x};
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __hip_atomic_store(&sh.prod[w], (uint32_t)(last < nA ? last : nA), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        if (out_global && (q == (kWindow >> sub_shift) - 1 || tend >= T)) {
-            // the window's rows are in lanes kWave - (tend - wb) .. 63 (lanes
-            // without a row of this window write slot row 0, which no
-            // consumer reads: no lane-conditional branch)
-            const int ws = tend - wb;
-            int r = tend - 2 * kWave + 1 + lane;
-            r = (lane >= kWave - ws && r >= 1 && r <= nA) ? r : 0;
-            out_slot[r] = Pair2<AT>{col_dp, col_x};
-            if (last >= 1) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_store(out_flag, (uint32_t)(last < nA ? last : nA), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-}
-
-// Persistent workgroups of G waves.  A workgroup claims a group g of G
-// consecutive strips from an atomic ticket (wave 0 claims, LDS broadcasts),
-// so the group it waits for has always been claimed by a running workgroup:
-// no co-residency assumption, no deadlock.  Inside the group, wave w sweeps
-// strip g*G + w.
-//
-// Two global slots suffice: group g+2 writes row r of its boundary only
-// after group g+1 has read row r from the slot both use (it reads a row
-// before its own last wave can produce that row).
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP>
-__global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restrict__ rowsA,
-                                                             const CT *__restrict__ rowsB, int nA, int nB,
-                                                             CostArgs<CT> ca, Pair2<AT> *bnd, uint32_t *flags,
-                                                             uint32_t *ticket, uint32_t *err, int nStrips,
-                                                             const CT *beta_ptr, AT *out, AT *dump, int sub_shift)
-{
-    __shared__ GroupShared<AT, G> sh;
-    const int w = (int)(threadIdx.x / kWave);
-    const CT beta = kShifted<AT> ? beta_ptr[0] : CT(0);
-    const int nGroups = (nStrips + G - 1) / G;
-    for (;;) {
-        __syncthreads();  // the previous group is done with the LDS
-        // Every thread takes part in the claim and only thread 0 counts, so
-        // there is no branch around the atomic; wave 0's lane-0 value is the
-        // group, published through LDS.
-        const uint32_t mine = atomicAdd(ticket, threadIdx.x == 0 ? 1u : 0u);
-        __hip_atomic_store(&sh.ticket[w], (uint32_t)__builtin_amdgcn_readlane((int)mine, 0), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_store(&sh.prod[w], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_store(&sh.cons[w], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __syncthreads();
-        const int g = (int)__hip_atomic_load(&sh.ticket[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (g >= nGroups) break;
-        const int s = g * G + w;
-        if (s < nStrips)
-            sweep_strip<CT, AT, DIMT, PM, K, G, DUMP>(sh, w, g, s, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
-                                                      nStrips, beta, out, dump, sub_shift);
-    }
-}
 
 template <typename CT, typename AT, int DIMT, int PM, int K, int G>
 static hipError_t launch_kg(const WavefrontArgs &a, const CostParams &cp, hipStream_t st)
@@ -335,19 +37,19 @@ static hipError_t launch_kg(const WavefrontArgs &a, const CostParams &cp, hipStr
     if (a.dump) {
         // cell dumps are a validation aid: narrow strips, one wave per group
         if constexpr (K <= 2 && G == 1) {
-            hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, G, true>), dim3(a.grid), dim3(kWave * G), 0,
+            hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, G, true, false>), dim3(a.grid), dim3(kWave * G), 0,
                                st, (const CT *)a.rowsA, (const CT *)a.rowsB, (int)a.nA, (int)a.nB,
                                CostArgs<CT>::make(cp), (Pair2<AT> *)a.bnd, a.flags, a.ticket, a.ticket + 1,
-                               (int)a.nStrips, (const CT *)a.beta, (AT *)a.out, (AT *)a.dump, a.sub_shift);
+                               (int)a.nStrips, (const CT *)a.beta, (AT *)a.out, (AT *)a.dump, a.sub_shift, TileIO<AT>{});
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
         }
     }
-    hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, G, false>), dim3(a.grid), dim3(kWave * G), 0, st,
+    hipLaunchKernelGGL((wavefront_kernel<CT, AT, DIMT, PM, K, G, false, false>), dim3(a.grid), dim3(kWave * G), 0, st,
                        (const CT *)a.rowsA, (const CT *)a.rowsB, (int)a.nA, (int)a.nB, CostArgs<CT>::make(cp),
                        (Pair2<AT> *)a.bnd, a.flags, a.ticket, a.ticket + 1, (int)a.nStrips, (const CT *)a.beta,
-                       (AT *)a.out, nullptr, a.sub_shift);
+                       (AT *)a.out, nullptr, a.sub_shift, TileIO<AT>{});
     return hipGetLastError();
 }
 
@@ -359,37 +61,6 @@ static hipError_t launch_k(const WavefrontArgs &a, const CostParams &cp, hipStre
     case 4: return launch_kg<CT, AT, DIMT, PM, K, 4>(a, cp, st);
     case 8: return launch_kg<CT, AT, DIMT, PM, K, 8>(a, cp, st);
     default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename CT, typename AT, int DIMT, int PM, int K, int G>
-static int occupancy_kg()
-{
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wavefront_kernel<CT, AT, DIMT, PM, K, G, false>,
-                                                     kWave * G, 0) != hipSuccess)
-        return 0;
-    return blocks;
-}
-
-template <typename CT, typename AT, int DIMT, int PM, int K, int G>
-static size_t scratch_kg()
-{
-    hipFuncAttributes attr{};
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(wavefront_kernel<CT, AT, DIMT, PM, K, G, false>)) !=
-        hipSuccess)
-        return (size_t)-1;
-    return attr.localSizeBytes;
-}
-
-template <typename CT, typename AT, int DIMT, int PM, int K>
-static int occupancy_k(int G)
-{
-    switch (G) {
-    case 1: return occupancy_kg<CT, AT, DIMT, PM, K, 1>();
-    case 4: return occupancy_kg<CT, AT, DIMT, PM, K, 4>();
-    case 8: return occupancy_kg<CT, AT, DIMT, PM, K, 8>();
-    default: return 0;
     }
 }
 
@@ -412,11 +83,6 @@ hipError_t launch_offset(Prec prec, const CostParams &cp, const void *rowsA, int
     });
 }
 
-// Strip widths compiled for a sample dimension: beyond 16 components a lane
-// holds at most two columns (wider strips would not fit the register file).
-template <int DIMT, int K>
-constexpr bool kStripCompiled = DIMT <= 16 || K <= 2;
-
 hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, hipStream_t st)
 {
     return by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
@@ -437,12 +103,12 @@ hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const Wavefr
 size_t wavefront_scratch_bytes(Prec prec, const CostParams &cp, int K, int G)
 {
     size_t bytes = (size_t)-1;
-    by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
+    (void)by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
         auto pick = [&]<int KK>() -> size_t {
             switch (G) {
-            case 1: return scratch_kg<CT, AT, DIMT, PM, KK, 1>();
-            case 4: return scratch_kg<CT, AT, DIMT, PM, KK, 4>();
-            case 8: return scratch_kg<CT, AT, DIMT, PM, KK, 8>();
+            case 1: return scratch_kg<CT, AT, DIMT, PM, KK, 1, false>();
+            case 4: return scratch_kg<CT, AT, DIMT, PM, KK, 4, false>();
+            case 8: return scratch_kg<CT, AT, DIMT, PM, KK, 8, false>();
             default: return (size_t)-1;
             }
         };
@@ -467,13 +133,13 @@ int wavefront_max_workers(Prec prec, const CostParams &cp, int K, int G)
     int per_cu = 0;
     hipError_t e = by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
         switch (K) {
-        case 1: per_cu = occupancy_k<CT, AT, DIMT, PM, 1>(G); break;
-        case 2: per_cu = occupancy_k<CT, AT, DIMT, PM, 2>(G); break;
+        case 1: per_cu = occupancy_k<CT, AT, DIMT, PM, 1, false>(G); break;
+        case 2: per_cu = occupancy_k<CT, AT, DIMT, PM, 2, false>(G); break;
         case 4:
-            if constexpr (kStripCompiled<DIMT, 4>) per_cu = occupancy_k<CT, AT, DIMT, PM, 4>(G);
+            if constexpr (kStripCompiled<DIMT, 4>) per_cu = occupancy_k<CT, AT, DIMT, PM, 4, false>(G);
             break;
         case 8:
-            if constexpr (kStripCompiled<DIMT, 8>) per_cu = occupancy_k<CT, AT, DIMT, PM, 8>(G);
+            if constexpr (kStripCompiled<DIMT, 8>) per_cu = occupancy_k<CT, AT, DIMT, PM, 8, false>(G);
             break;
         default: break;
         }

@@ -222,3 +222,39 @@ def test_tune_host_checks(L):
     assert L.twed_pair_tune(fake, fake, 10, fake, fake, 10, C.byref(prm), None, 0, None,
                             C.byref(k), C.byref(g)) == WORKSPACE
     L.twed_tune_clear()
+
+
+def test_tile_and_path_host_checks(L):
+    c = ctypes
+    prm = tw.make_params(dim=2)
+    ws_need = L.twed_pair_tile_workspace_size(10, 10, c.byref(prm))
+    assert ws_need > 0
+    assert L.twed_pair_tile_workspace_size(0, 10, c.byref(prm)) == 0
+    assert L.twed_pair_tile_workspace_size(10, 10, c.byref(tw.make_params(precision="f32"))) == 0
+
+    def tile(r0, r1, c0, c1, top=None, left=None, p=prm, ws=None, wsb=0):
+        return L.twed_pair_tile(FAKE, FAKE, 20, FAKE, FAKE, 20, c.byref(p), r0, r1, c0, c1, top, left, None, None,
+                                None, ws, wsb, None)
+
+    assert tile(5, 5, 0, 10) == INVALID          # empty block
+    assert tile(0, 21, 0, 10) == INVALID         # past nA
+    assert tile(3, 10, 0, 10) == INVALID         # top row missing
+    assert tile(0, 10, 4, 10) == INVALID         # left column missing
+    assert tile(0, 10, 0, 10, p=tw.make_params(dim=2, precision="f32")) == UNSUPPORTED
+    assert tile(0, 10, 0, 10) == WORKSPACE
+    assert L.twed_pair_tile(None, FAKE, 20, FAKE, FAKE, 20, c.byref(prm), 0, 1, 0, 1, None, None, None, None, None,
+                            None, 0, None) == INVALID
+    need = L.twed_pair_path_workspace_size(100, 90, c.byref(prm), 0)
+    assert need > 0
+    assert L.twed_pair_path_workspace_size(100, 90, c.byref(prm), -1) == 0
+    # blocks of 64: checkpoints every 64 rows and every 64 columns (78 each)
+    assert L.twed_pair_path_workspace_size(5000, 5000, c.byref(prm), 64) >= 2 * 78 * 5001 * 16
+
+    def path(block=0, out=FAKE, pth=FAKE, n=FAKE, p=prm, wsb=0):
+        return L.twed_pair_path(FAKE, FAKE, 100, FAKE, FAKE, 90, c.byref(p), block, out, pth, n, None, wsb, None)
+
+    assert path(block=-1) == INVALID
+    assert path(out=None) == INVALID
+    assert path(pth=None) == INVALID
+    assert path(p=tw.make_params(dim=2, precision="f32")) == UNSUPPORTED
+    assert path() == WORKSPACE
