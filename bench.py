@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--cpu-n", type=int, default=30000, help="prefix length of the CPU oracle sample")
     ap.add_argument("--no-rn", action="store_true", help="skip the R^28 single-query measurement")
+    ap.add_argument("--no-tiles", action="store_true", help="skip the column-shard and alignment-path measurements")
     ap.add_argument("--rn-all", action="store_true", help="also time the 60000 x 60000 R^28 all-pairs matrix")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (counter calibration)")
@@ -291,6 +292,38 @@ def main():
             "roofline_frac": round(OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / VALU_PEAK_TOPS, 4),
         }
         log(f"batch: {result['batched_all_pairs']}")
+
+    # ---- one GPU's share of a column-sharded sweep, and the alignment path
+    if not args.no_tiles:
+        shard = 125_000
+        if n >= 2 * shard:
+            def tstep(c0):
+                left = None if c0 == 0 else shard_right
+                return tw.twed_pair_tile(A, TA, B, TB, 0, n, c0, c0 + shard, None, left, c.nu, c.lam, c.p,
+                                         "f32_acc64", bottom=False)
+            _, _, shard_right = tstep(0)
+            twall, tper = time_steps(lambda: tstep(shard), max(args.steps, 3), 1, torch)
+            tk = float(np.mean(tper))
+            result["column_shard"] = {
+                "workload": f"rows 1..{n} x columns {shard + 1}..{2 * shard} of the headline pair (one of eight "
+                            f"column shards): left boundary column in, right boundary column out",
+                "ms_per_step": round(tk * 1e3, 3), "GCUPS": round(float(n) * shard / tk / 1e9, 3)}
+            log(f"column shard: {result['column_shard']}")
+        pn = min(n, 100_000)
+        pc = c.prefix(pn)
+        pA, pTA, pB, pTB = f32(pc.A), f32(pc.TA), f32(pc.B), f32(pc.TB)
+        pprm = tw.make_params(c.nu, c.lam, c.p, 8, "f32_acc64")
+        pws = torch.empty(max(tw.binding.twed_pair_path_workspace_size(pn, pn, pprm), 256), dtype=torch.uint8,
+                          device=dev)
+        _, path = tw.twed_pair_path(pA, pTA, pB, pTB, c.nu, c.lam, c.p, "f32_acc64", workspace=pws)
+        pwall, _ = time_steps(lambda: tw.twed_pair_path(pA, pTA, pB, pTB, c.nu, c.lam, c.p, "f32_acc64",
+                                                        workspace=pws), 2, 0, torch)
+        result["alignment_path"] = {
+            "workload": f"8-D pair n=m={pn} (prefix of the headline pair), FP32 costs + FP64 accumulators, "
+                        f"blocks of 4096",
+            "s_per_path": round(pwall / 2, 4), "path_cells": int(path.shape[0]),
+            "forward_GCUPS_equiv": round(float(pn) * pn / (pwall / 2) / 1e9, 3)}
+        log(f"path: {result['alignment_path']}")
 
     # ---- R^28: one query against 60,000 series of 28 samples in R^28 (FP64, L2)
     if not args.no_rn:

@@ -264,6 +264,14 @@ def twed_pair_tile(A, TA, B, TB, r0, r1, c0, c1, top=None, left=None, nu=1e-3, l
     return corner, bot, rig
 
 
+def twed_pair_path_workspace_size(nA, nB, prm: TwedParams, block=0) -> int:
+    return load_library().twed_pair_path_workspace_size(int(nA), int(nB), ctypes.byref(prm), int(block))
+
+
+def twed_pair_tile_workspace_size(rows, cols, prm: TwedParams) -> int:
+    return load_library().twed_pair_tile_workspace_size(int(rows), int(cols), ctypes.byref(prm))
+
+
 def twed_pair_path(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", block=0, strip_k=0,
                    workspace=None, stream=None):
     """(distance, path): a one-element float64 tensor and an (L, 2) int64
