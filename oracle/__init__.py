@@ -58,6 +58,12 @@ class Oracle:
         lib.twed_oracle_path.argtypes = lib.twed_oracle_matrix.argtypes[:-1] + [_i64_p]
         lib.twed_oracle_path_cost.restype = ctypes.c_double
         lib.twed_oracle_path_cost.argtypes = lib.twed_oracle_matrix.argtypes[:-1] + [_i64_p, ctypes.c_int64]
+        lib.twed_oracle_dtw.restype = ctypes.c_double
+        lib.twed_oracle_dtw.argtypes = [_dbl_p, ctypes.c_int64, _dbl_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_double]
+        for f in (lib.twed_oracle_edit, lib.twed_oracle_lcs):
+            f.restype = ctypes.c_int64
+            f.argtypes = [_dbl_p, ctypes.c_int64, _dbl_p, ctypes.c_int64]
         lib.twed_oracle_mutant.restype = ctypes.c_int32
         self.lib = lib
         self.mutant = lib.twed_oracle_mutant()
@@ -135,6 +141,24 @@ class Oracle:
         keep, args = self._args(A, TA, B, TB, nu, lam, p)
         P = np.ascontiguousarray(np.asarray(path, dtype=np.int64).reshape(-1, 2))
         return self.lib.twed_oracle_path_cost(*args, P.ctypes.data_as(_i64_p), P.shape[0])
+
+    def dtw(self, A, B, p=1.0):
+        """Dynamic time warping distance with the Lp point distance."""
+        A, B = self._pts(A), self._pts(B)
+        if A.shape[1] != B.shape[1]:
+            raise ValueError("shape mismatch")
+        return self.lib.twed_oracle_dtw(A.ctypes.data_as(_dbl_p), A.shape[0], B.ctypes.data_as(_dbl_p),
+                                        B.shape[0], A.shape[1], float(p))
+
+    def edit(self, A, B):
+        """Levenshtein distance between two 1-D sequences of tokens."""
+        A, B = self._vec(A), self._vec(B)
+        return int(self.lib.twed_oracle_edit(A.ctypes.data_as(_dbl_p), len(A), B.ctypes.data_as(_dbl_p), len(B)))
+
+    def lcs(self, A, B):
+        """Length of a longest common subsequence of two 1-D token sequences."""
+        A, B = self._vec(A), self._vec(B)
+        return int(self.lib.twed_oracle_lcs(A.ctypes.data_as(_dbl_p), len(A), B.ctypes.data_as(_dbl_p), len(B)))
 
     def pairs(self, X, TX, offX, Y, TY, offY, pairs, nu, lam, p=1.0, threads=None):
         """TWED for explicit (i, j) pairs of two packed collections (CSR offsets)."""

@@ -418,6 +418,95 @@ double twed_oracle_path_cost(const double *A, const double *TA, int64_t nA,
     return ok ? cost : NAN;
 }
 
+/* ---- sibling dynamic programs -----------------------------------------------
+ *
+ * Section "Generalized Dynamic Programming Extensions" (its "Direct
+ * Extension: LCS") notes that other programs whose cells need only the cells
+ * above, to the left and diagonally above-left can be swept the same way.
+ * Their plain definitions, two rows of memory each:
+ *
+ *   DTW   D[0][0] = 0, D[i][0] = D[0][j] = +inf,
+ *         D[i][j] = delta(A_i, B_j) + min(D[i-1][j], D[i][j-1], D[i-1][j-1])
+ *   edit  E[i][0] = i, E[0][j] = j,
+ *         E[i][j] = min(E[i-1][j] + 1, E[i][j-1] + 1, E[i-1][j-1] + [A_i != B_j])
+ *   LCS   L[i][0] = L[0][j] = 0,
+ *         L[i][j] = A_i == B_j ? L[i-1][j-1] + 1 : max(L[i-1][j], L[i][j-1])
+ *
+ * (samples 1-based as in the TWED definition; edit and LCS compare 1-D
+ * samples for equality).
+ */
+double twed_oracle_dtw(const double *A, int64_t nA, const double *B, int64_t nB, int32_t dim, double p)
+{
+    if (nA < 1 || nB < 1 || dim < 1) return NAN;
+    double *prev = (double *)malloc((size_t)(nB + 1) * sizeof(double));
+    double *cur = (double *)malloc((size_t)(nB + 1) * sizeof(double));
+    if (!prev || !cur) {
+        free(prev); free(cur);
+        return NAN;
+    }
+    prev[0] = 0.0;
+    for (int64_t j = 1; j <= nB; j++) prev[j] = INFINITY;
+    for (int64_t i = 1; i <= nA; i++) {
+        cur[0] = INFINITY;
+        for (int64_t j = 1; j <= nB; j++) {
+            const double d = point_dist(A + (i - 1) * dim, B + (j - 1) * dim, dim, p);
+            cur[j] = d + min3(prev[j], cur[j - 1], prev[j - 1]);
+        }
+        double *t = prev; prev = cur; cur = t;
+    }
+    double r = prev[nB];
+    free(prev); free(cur);
+    return r;
+}
+
+int64_t twed_oracle_edit(const double *A, int64_t nA, const double *B, int64_t nB)
+{
+    if (nA < 1 || nB < 1) return -1;
+    int64_t *prev = (int64_t *)malloc((size_t)(nB + 1) * sizeof(int64_t));
+    int64_t *cur = (int64_t *)malloc((size_t)(nB + 1) * sizeof(int64_t));
+    if (!prev || !cur) {
+        free(prev); free(cur);
+        return -1;
+    }
+    for (int64_t j = 0; j <= nB; j++) prev[j] = j;
+    for (int64_t i = 1; i <= nA; i++) {
+        cur[0] = i;
+        for (int64_t j = 1; j <= nB; j++) {
+            int64_t v = prev[j] + 1;
+            if (cur[j - 1] + 1 < v) v = cur[j - 1] + 1;
+            const int64_t m = prev[j - 1] + (A[i - 1] != B[j - 1]);
+            if (m < v) v = m;
+            cur[j] = v;
+        }
+        int64_t *t = prev; prev = cur; cur = t;
+    }
+    int64_t r = prev[nB];
+    free(prev); free(cur);
+    return r;
+}
+
+int64_t twed_oracle_lcs(const double *A, int64_t nA, const double *B, int64_t nB)
+{
+    if (nA < 1 || nB < 1) return -1;
+    int64_t *prev = (int64_t *)calloc((size_t)(nB + 1), sizeof(int64_t));
+    int64_t *cur = (int64_t *)calloc((size_t)(nB + 1), sizeof(int64_t));
+    if (!prev || !cur) {
+        free(prev); free(cur);
+        return -1;
+    }
+    for (int64_t i = 1; i <= nA; i++) {
+        cur[0] = 0;
+        for (int64_t j = 1; j <= nB; j++) {
+            if (A[i - 1] == B[j - 1]) cur[j] = prev[j - 1] + 1;
+            else cur[j] = prev[j] > cur[j - 1] ? prev[j] : cur[j - 1];
+        }
+        int64_t *t = prev; prev = cur; cur = t;
+    }
+    int64_t r = prev[nB];
+    free(prev); free(cur);
+    return r;
+}
+
 /* ---- batches: independent pairs spread over threads ---------------------- */
 
 typedef struct {
