@@ -203,6 +203,48 @@ twed_status twed_pair_path(const void *A, const void *TA, int64_t nA,
                            double *out, int64_t *path, int64_t *path_len,
                            void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---- sibling dynamic programs (section "Generalized Dynamic Programming
+ * Extensions", its "Direct Extension: LCS": programs whose cells need only
+ * the cells above, to the left and up-left run on the same band sweep) ------
+ * TWED_DP_DTW   dynamic time warping: D(i, j) = d(A_i, B_j) + min(D(i-1, j),
+ *               D(i, j-1), D(i-1, j-1)), D(0, 0) = 0, +inf on the rest of row
+ *               0 and column 0; d is the Lp distance of twed_params (dim, p).
+ * TWED_DP_EDIT  edit (Levenshtein) distance of two 1-D token sequences
+ *               (samples compared for equality; dim must be 1).
+ * TWED_DP_LCS   length of a longest common subsequence of two 1-D token
+ *               sequences (dim 1), from the indel distance nA + nB - 2*LCS.
+ * Timestamps, nu and lambda are not used.  Samples are double for TWED_F64
+ * and float for TWED_F32_ACC64 (the only precisions; tokens should be exact
+ * integers in that type); results are one double on the device. */
+typedef enum {
+    TWED_DP_DTW = 1,
+    TWED_DP_EDIT = 2,
+    TWED_DP_LCS = 3
+} twed_dp_kind;
+
+/* One pair.  Errors: TWED_ERR_INVALID for an unknown kind, null pointers or
+ * empty series; TWED_ERR_UNSUPPORTED for dim != 1 with EDIT / LCS, another
+ * precision, strip_k other than 0, 1 or 8, or series >= 2^31;
+ * TWED_ERR_WORKSPACE if ws_bytes < twed_dp_workspace_size(...). */
+size_t twed_dp_workspace_size(int32_t kind, int64_t nA, int64_t nB, const twed_params *prm);
+
+twed_status twed_dp(int32_t kind, const void *A, int64_t nA, const void *B, int64_t nB,
+                    const twed_params *prm, double *out,
+                    void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* One optimal alignment of the pair, as twed_pair_path (same path format,
+ * tie order, block checkpoints and stream synchronisation).  For the edit and
+ * LCS kinds the path may run along row 0 or column 0; for LCS the diagonal
+ * steps into cells (i, j) with A_i == B_j give a longest common subsequence.
+ * out receives the value as twed_dp. */
+size_t twed_dp_path_workspace_size(int32_t kind, int64_t nA, int64_t nB, const twed_params *prm,
+                                   int64_t block);
+
+twed_status twed_dp_path(int32_t kind, const void *A, int64_t nA, const void *B, int64_t nB,
+                         const twed_params *prm, int64_t block,
+                         double *out, int64_t *path, int64_t *path_len,
+                         void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* ---- many pairs (the paper's batch mode, section "cuTWED Implementation
  * Remarks"; the symmetric case computes only the upper triangle, as the
  * section "Validation using Real Datasets" anticipates) ---------------------

@@ -25,6 +25,7 @@ EXPORTS = [
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
     "twed_pair_tune", "twed_tune_clear",
     "twed_pair_tile_workspace_size", "twed_pair_tile", "twed_pair_path_workspace_size", "twed_pair_path",
+    "twed_dp_workspace_size", "twed_dp", "twed_dp_path_workspace_size", "twed_dp_path",
     "twed_embed_param_count", "twed_embed_max_length", "twed_embed_workspace_size", "twed_embed_forward",
     "twed_embed_loss_grad", "twed_embed_adamw", "twed_knn_index_storage_size", "twed_knn_index_create",
     "twed_knn_index_build_workspace_size", "twed_knn_index_build", "twed_knn_workspace_size", "twed_knn",
@@ -88,6 +89,15 @@ def load_library(path: str = LIB_PATH):
     L.twed_pair_path.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                  _vp]
     L.twed_pair_path.restype = ctypes.c_int
+    L.twed_dp_workspace_size.argtypes = [ctypes.c_int32, _i64, _i64, _pp]
+    L.twed_dp_workspace_size.restype = ctypes.c_size_t
+    L.twed_dp.argtypes = [ctypes.c_int32, _vp, _i64, _vp, _i64, _pp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.twed_dp.restype = ctypes.c_int
+    L.twed_dp_path_workspace_size.argtypes = [ctypes.c_int32, _i64, _i64, _pp, _i64]
+    L.twed_dp_path_workspace_size.restype = ctypes.c_size_t
+    L.twed_dp_path.argtypes = [ctypes.c_int32, _vp, _i64, _vp, _i64, _pp, _i64, _vp, _vp, _vp, _vp,
+                               ctypes.c_size_t, _vp]
+    L.twed_dp_path.restype = ctypes.c_int
     L.twed_tune_clear.restype = None
     L.twed_batch_max_short_length.argtypes = [ctypes.c_int32]
     L.twed_batch_max_short_length.restype = ctypes.c_int64
@@ -289,6 +299,50 @@ def twed_pair_path(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", block
     _check(L.twed_pair_path(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
                             ctypes.byref(prm), int(block), out.data_ptr(), path.data_ptr(), n.data_ptr(),
                             ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out, path[: int(n.item())]
+
+
+DP_KINDS = {"dtw": 1, "edit": 2, "lcs": 3}
+
+
+def _dp_operands(A, B, precision):
+    dt = input_dtype(precision)
+    A2 = A if A.dim() == 2 else A.reshape(-1, 1)
+    B2 = B if B.dim() == 2 else B.reshape(-1, 1)
+    _dev(A2, dt, "A"); _dev(B2, dt, "B")
+    if A2.shape[1] != B2.shape[1]:
+        raise ValueError("shape mismatch")
+    return A2, B2, A2.shape[0], B2.shape[0], A2.shape[1]
+
+
+def twed_dp(kind, A, B, p=1.0, precision="f64", strip_k=0, workspace=None, stream=None):
+    """DTW distance ("dtw", Lp point distance), edit distance ("edit") or LCS
+    length ("lcs") of two device series, as a one-element float64 tensor."""
+    torch = _torch()
+    k = DP_KINDS[kind] if isinstance(kind, str) else int(kind)
+    A2, B2, nA, nB, dim = _dp_operands(A, B, precision)
+    prm = make_params(0.0, 0.0, p, dim, precision, "auto", strip_k)
+    L = load_library()
+    ws = _workspace(L.twed_dp_workspace_size(k, nA, nB, ctypes.byref(prm)), A2.device, workspace)
+    out = torch.empty(1, dtype=torch.float64, device=A2.device)
+    _check(L.twed_dp(k, A2.data_ptr(), nA, B2.data_ptr(), nB, ctypes.byref(prm), out.data_ptr(), ws.data_ptr(),
+                     ws.numel(), _stream(stream)))
+    return out
+
+
+def twed_dp_path(kind, A, B, p=1.0, precision="f64", block=0, strip_k=0, workspace=None, stream=None):
+    """(value, path) for a twed_dp kind; path as twed_pair_path."""
+    torch = _torch()
+    k = DP_KINDS[kind] if isinstance(kind, str) else int(kind)
+    A2, B2, nA, nB, dim = _dp_operands(A, B, precision)
+    prm = make_params(0.0, 0.0, p, dim, precision, "auto", strip_k)
+    L = load_library()
+    ws = _workspace(L.twed_dp_path_workspace_size(k, nA, nB, ctypes.byref(prm), int(block)), A2.device, workspace)
+    out = torch.empty(1, dtype=torch.float64, device=A2.device)
+    path = torch.empty((nA + nB + 1, 2), dtype=torch.int64, device=A2.device)
+    n = torch.zeros(1, dtype=torch.int64, device=A2.device)
+    _check(L.twed_dp_path(k, A2.data_ptr(), nA, B2.data_ptr(), nB, ctypes.byref(prm), int(block), out.data_ptr(),
+                          path.data_ptr(), n.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
     return out, path[: int(n.item())]
 
 

@@ -15,8 +15,11 @@ namespace {
 
 // One thread: the walk is a chain of dependent loads.  st = {r, c, n, status}
 // in global coordinates; status 0 running, 1 reached (0, 0), -1 failed.
+// With free_edges (edit and indel distances, whose row 0 and column 0 are
+// finite) a walk that reaches row 0 or column 0 follows it to (0, 0); for
+// TWED and DTW those cells are +inf and reaching one is an error.
 __global__ void walk_kernel(const uint8_t *__restrict__ dirs, int64_t r0, int64_t c0, int K, int64_t T,
-                            int64_t *st, int64_t *rev, int64_t cap)
+                            int64_t *st, int64_t *rev, int64_t cap, int free_edges)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     if (st[3] != 0) return;
@@ -24,15 +27,20 @@ __global__ void walk_kernel(const uint8_t *__restrict__ dirs, int64_t r0, int64_
     int64_t status = 0;
     const int64_t W = (int64_t)kWave * K;
     for (;;) {
-        if (r == 0 && c == 0) {
-            if (n >= cap) {
+        if (r == 0 || c == 0) {
+            if (!(r == 0 && c == 0) && !free_edges) {
                 status = -1;
                 break;
             }
-            rev[2 * n] = 0;
-            rev[2 * n + 1] = 0;
-            ++n;
-            status = 1;
+            while (n < cap) {
+                rev[2 * n] = r;
+                rev[2 * n + 1] = c;
+                ++n;
+                if (r == 0 && c == 0) break;
+                if (r > 0) --r;
+                else --c;
+            }
+            status = (r == 0 && c == 0 && n <= cap) ? 1 : -1;
             break;
         }
         const int64_t rr = r - r0, cc = c - c0;
@@ -99,9 +107,40 @@ hipError_t launch_walk_init(int64_t *st, int64_t nA, int64_t nB, hipStream_t s)
 }
 
 hipError_t launch_walk(const uint8_t *dirs, int64_t r0, int64_t c0, int K, int64_t T, int64_t *st, int64_t *rev,
-                       int64_t cap, hipStream_t s)
+                       int64_t cap, bool free_edges, hipStream_t s)
 {
-    hipLaunchKernelGGL(walk_kernel, dim3(1), dim3(1), 0, s, dirs, r0, c0, K, T, st, rev, cap);
+    hipLaunchKernelGGL(walk_kernel, dim3(1), dim3(1), 0, s, dirs, r0, c0, K, T, st, rev, cap, free_edges ? 1 : 0);
+    return hipGetLastError();
+}
+
+namespace {
+// cells[i] = (i, i): row 0 or column 0 of the edit and indel distances.
+__global__ void index_cells_kernel(double *cells, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        cells[2 * i] = (double)i;
+        cells[2 * i + 1] = (double)i;
+    }
+}
+
+// LCS length from the indel distance: (nA + nB - I) / 2.
+__global__ void lcs_finish_kernel(double *out, int64_t nA, int64_t nB)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = ((double)(nA + nB) - out[0]) * 0.5;
+}
+}  // namespace
+
+hipError_t launch_index_cells(void *cells, int64_t n, hipStream_t s)
+{
+    int64_t g = (n + 256) / 256;
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(index_cells_kernel, dim3((int)g), dim3(256), 0, s, (double *)cells, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_lcs_finish(double *out, int64_t nA, int64_t nB, hipStream_t s)
+{
+    hipLaunchKernelGGL(lcs_finish_kernel, dim3(1), dim3(1), 0, s, out, nA, nB);
     return hipGetLastError();
 }
 

@@ -57,8 +57,8 @@ __global__ __launch_bounds__(256) void stage_kernel(const CT *__restrict__ X, co
                 cur[k] = (r >= 1 && k < dim) ? X[(b + r - 1) * dim + k] : CT(0);
                 prev[k] = ((r >= 2 || (r == 1 && first_prev)) && k < dim) ? X[(b + r - 2) * dim + k] : CT(0);
             }
-            const CT tc = r >= 1 ? T[b + r - 1] : CT(0);
-            const CT tp = (r >= 2 || (r == 1 && first_prev)) ? T[b + r - 2] : CT(0);
+            const CT tc = (r >= 1 && T) ? T[b + r - 1] : CT(0);
+            const CT tp = ((r >= 2 || (r == 1 && first_prev)) && T) ? T[b + r - 2] : CT(0);
             CT del = CT(0);
             if (r >= 1) {
                 const CT d = point_dist<DIMT, PM, CT>(cur, prev, ca.p, ca.invp);

@@ -110,11 +110,14 @@ hipError_t launch_tile(Prec prec, const CostParams &cp, int K, const WavefrontAr
         }
     });
     if (e != hipSuccess) return e;
-    if (t.bottom || t.right || t.ckrow || t.ckcol) {
-        hipLaunchKernelGGL(tile_edges_kernel, dim3(64), dim3(256), 0, st, t, a.nA, a.nB);
-        e = hipGetLastError();
-    }
-    return e;
+    return launch_tile_edges(a.nA, a.nB, t, st);
+}
+
+hipError_t launch_tile_edges(int64_t nA, int64_t nB, const TileArgs &t, hipStream_t st)
+{
+    if (!(t.bottom || t.right || t.ckrow || t.ckcol)) return hipSuccess;
+    hipLaunchKernelGGL(tile_edges_kernel, dim3(64), dim3(256), 0, st, t, nA, nB);
+    return hipGetLastError();
 }
 
 size_t tile_scratch_bytes(Prec prec, const CostParams &cp, int K, int G)

@@ -48,16 +48,26 @@ struct Sweep {
 // The widest strip whose kernel keeps to registers and still leaves about
 // 1.5 strips per SIMD, in the widest non-spilling group that leaves about one
 // group per CU (the rules of the pair sweep).
-Sweep tile_sweep(int strip_k, int64_t nB, Prec prec, const CostParams &cp)
+// The recurrence a sweep runs: kRecTwed, or a sibling (kRecDtw, kRecEdit,
+// kRecIndel; see twed_device.h), whose kernels exist for K in {1, 8} and G
+// in {1, 8} only.
+size_t sweep_scratch(int rec, Prec prec, const CostParams &cp, int K, int G)
 {
+    return rec == kRecTwed ? tile_scratch_bytes(prec, cp, K, G) : dp_scratch_bytes(rec, prec, cp, K, G);
+}
+
+Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &cp)
+{
+    const bool sib = rec != kRecTwed;
     int K = 1;
     if (strip_k > 0) {
         K = strip_k;
     } else {
         const int64_t want = (int64_t)simds() * 3 / 2;
         for (int k : {8, 4, 2}) {
+            if (sib && k != 8) continue;
             const int64_t strips = (nB + 64 * k - 1) / (64 * k);
-            if (strips >= want && tile_scratch_bytes(prec, cp, k, 1) == 0) {
+            if (strips >= want && sweep_scratch(rec, prec, cp, k, 1) == 0) {
                 K = k;
                 break;
             }
@@ -66,11 +76,13 @@ Sweep tile_sweep(int strip_k, int64_t nB, Prec prec, const CostParams &cp)
     const int64_t nStrips = (nB + 64 * K - 1) / (64 * K);
     const int64_t cus = std::max(1, simds() / 4);
     int G = 1;
-    for (int g : {8, 4})
-        if (nStrips * 10 >= (int64_t)g * cus * 9 && tile_scratch_bytes(prec, cp, K, g) == 0) {
+    for (int g : {8, 4}) {
+        if (sib && g != 8) continue;
+        if (nStrips * 10 >= (int64_t)g * cus * 9 && sweep_scratch(rec, prec, cp, K, g) == 0) {
             G = g;
             break;
         }
+    }
     return Sweep{K, G};
 }
 
@@ -92,8 +104,8 @@ void take_sweep(Carver &c, SweepBuffers &b, Prec prec, int dimt, int64_t nA, int
     b.tmp = c.take(8);
 }
 
-twed_status run_tile(Prec prec, const CostParams &cp, Sweep sw, const void *rowsA, const void *rowsB, int64_t nA,
-                     int64_t nB, const SweepBuffers &b, const TileArgs &t, void *out, hipStream_t st)
+twed_status run_tile(int rec, Prec prec, const CostParams &cp, Sweep sw, const void *rowsA, const void *rowsB,
+                     int64_t nA, int64_t nB, const SweepBuffers &b, const TileArgs &t, void *out, hipStream_t st)
 {
     WavefrontArgs w{};
     w.rowsA = rowsA;
@@ -109,10 +121,12 @@ twed_status run_tile(Prec prec, const CostParams &cp, Sweep sw, const void *rows
     w.dump = nullptr;
     w.group = sw.G;
     w.sub_shift = 4;
-    const int workers = tile_max_workers(prec, cp, sw.K, sw.G);
+    const int workers = rec == kRecTwed ? tile_max_workers(prec, cp, sw.K, sw.G)
+                                        : dp_max_workers(rec, prec, cp, sw.K, sw.G);
     if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
     w.grid = (int)std::min<int64_t>((w.nStrips + sw.G - 1) / sw.G, workers);
-    const hipError_t e = launch_tile(prec, cp, sw.K, w, t, st);
+    const hipError_t e = rec == kRecTwed ? launch_tile(prec, cp, sw.K, w, t, st)
+                                         : launch_dp(rec, prec, cp, sw.K, w, t, st);
     if (e != hipSuccess) return fail_hip(e, "tile sweep launch");
     return TWED_OK;
 }
@@ -134,34 +148,42 @@ struct PathGeometry {
     int64_t H, Wc, nr, nc;
 };
 
-PathGeometry path_geometry(const twed_params *prm, int64_t nA, int64_t nB, int64_t block, Prec prec,
+PathGeometry path_geometry(int rec, const twed_params *prm, int64_t nA, int64_t nB, int64_t block, Prec prec,
                            const CostParams &cp)
 {
     PathGeometry g{};
     const int64_t want = block > 0 ? block : kDefaultBlock;
-    g.fwd = tile_sweep(prm->strip_k, nB, prec, cp);
+    g.fwd = tile_sweep(rec, prm->strip_k, nB, prec, cp);
     const int64_t W = 64 * (int64_t)g.fwd.K;
     g.H = std::max<int64_t>(64, want);
     g.Wc = (std::max(want, W) + W - 1) / W * W;
     g.nr = (nA - 1) / g.H;
     g.nc = (nB - 1) / g.Wc;
-    g.blk = tile_sweep(0, std::min(g.Wc, nB), prec, cp);
+    g.blk = tile_sweep(rec, 0, std::min(g.Wc, nB), prec, cp);
     return g;
 }
 
+// Edit and indel distances start from finite row 0 / column 0 (i, i).
+bool finite_edges(int rec) { return rec == kRecEdit || rec == kRecIndel; }
+
 struct PathLayout {
     SweepBuffers b;
-    void *ckrow, *ckcol, *dirs;
+    void *ckrow, *ckcol, *dirs, *row0, *col0;
     int64_t *st;
     size_t total;
 };
 
-PathLayout path_layout(char *base, const twed_params *prm, int64_t nA, int64_t nB, const PathGeometry &g, Prec prec)
+PathLayout path_layout(char *base, int rec, const twed_params *prm, int64_t nA, int64_t nB, const PathGeometry &g,
+                       Prec prec)
 {
     Carver c{base};
     PathLayout L{};
     take_sweep(c, L.b, prec, dimt_for(prm->dim), nA, nB);
     L.st = (int64_t *)c.take(4 * sizeof(int64_t));
+    if (finite_edges(rec)) {
+        L.row0 = c.take((size_t)(nB + 1) * kCell);
+        L.col0 = c.take((size_t)(nA + 1) * kCell);
+    }
     L.ckrow = c.take((size_t)g.nr * (size_t)(nB + 1) * kCell);
     L.ckcol = c.take((size_t)g.nc * (size_t)(nA + 1) * kCell);
     const int64_t Wb = 64 * (int64_t)g.blk.K;
@@ -169,6 +191,106 @@ PathLayout path_layout(char *base, const twed_params *prm, int64_t nA, int64_t n
     L.dirs = c.take((size_t)strips * (size_t)(std::min(g.H, nA) + 64) * (size_t)Wb);
     L.total = c.used;
     return L;
+}
+
+// The path of one pair under recurrence `rec` (A/TA/B/TB as staged by
+// twed_pair; TA, TB null for the siblings).  Runs after argument checks.
+twed_status path_impl(int rec, const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                      const twed_params *prm, int64_t block, double *out, int64_t *path, int64_t *path_len,
+                      void *workspace, size_t ws_bytes, Prec prec, hipStream_t st)
+{
+    twed_status s;
+    const CostParams cp = cost_params(prm);
+    const PathGeometry g = path_geometry(rec, prm, nA, nB, block, prec, cp);
+    if (g.H > 0x40000000LL || g.Wc > 0x40000000LL) return fail(TWED_ERR_UNSUPPORTED, "block too large");
+    if ((s = check_workspace(workspace, ws_bytes, path_layout(nullptr, rec, prm, nA, nB, g, prec).total)) != TWED_OK)
+        return s;
+    const PathLayout L = path_layout((char *)workspace, rec, prm, nA, nB, g, prec);
+    const SweepBuffers &b = L.b;
+    hipError_t e;
+#define TRY(call, what)                                \
+    do {                                               \
+        e = (call);                                    \
+        if (e != hipSuccess) return fail_hip(e, what); \
+    } while (0)
+    // forward sweep of the whole pair, keeping checkpoint rows and columns
+    TRY(launch_stage(prec, cp, A, TA, nullptr, 1, nA, nA, nA + 1, b.rowsA, b.flags, b.zero_words, st), "staging");
+    TRY(launch_stage(prec, cp, B, TB, nullptr, 1, nB, nB, nB + 1, b.rowsB, nullptr, 0, st), "staging");
+    if (finite_edges(rec)) {
+        TRY(launch_index_cells(L.row0, nB, st), "boundary");
+        TRY(launch_index_cells(L.col0, nA, st), "boundary");
+    }
+    TileArgs t{};
+    t.top = L.row0;
+    t.left = L.col0;
+    t.dummy = b.dummy;
+    t.ckrow = g.nr > 0 ? L.ckrow : nullptr;
+    t.ckcol = g.nc > 0 ? L.ckcol : nullptr;
+    t.ck_rows = (int)g.H;
+    t.ck_cols = (int)g.Wc;
+    s = run_tile(rec, prec, cp, g.fwd, b.rowsA, b.rowsB, nA, nB, b, t, out, st);
+    if (s != TWED_OK) return s;
+    // backwards, block by block: sweep the block again recording moves, walk it
+    const int64_t cap = nA + nB + 1;
+    TRY(launch_walk_init(L.st, nA, nB, st), "walk set-up");
+    const size_t rb = row_bytes(prec, dimt_for(prm->dim));
+    int64_t hst[4] = {0, 0, 0, 0};
+    const int64_t max_blocks = g.nr + g.nc + 3;
+    for (int64_t it = 0;; ++it) {
+        TRY(hipMemcpyAsync(hst, L.st, sizeof(hst), hipMemcpyDeviceToHost, st), "walk state read");
+        TRY(hipStreamSynchronize(st), "walk state read");
+        if (hst[3] == 1) break;
+        if (hst[3] != 0 || it > max_blocks || hst[0] < 1 || hst[1] < 1)
+            return fail(TWED_ERR_DEVICE, "the path could not be followed (non-finite distance or a timed-out sweep)");
+        const int64_t br = (hst[0] - 1) / g.H, bc = (hst[1] - 1) / g.Wc;
+        const int64_t r0 = br * g.H, r1 = std::min(r0 + g.H, nA);
+        const int64_t c0 = bc * g.Wc, c1 = std::min(c0 + g.Wc, nB);
+        TRY(launch_zero32(b.flags, b.zero_words, st), "flag reset");
+        TileArgs u{};
+        u.dummy = b.dummy;
+        if (br > 0)
+            u.top = (const char *)L.ckrow + ((size_t)(br - 1) * (size_t)(nB + 1) + (size_t)c0) * kCell;
+        else if (L.row0)
+            u.top = (const char *)L.row0 + (size_t)c0 * kCell;
+        if (bc > 0)
+            u.left = (const char *)L.ckcol + ((size_t)(bc - 1) * (size_t)(nA + 1) + (size_t)r0) * kCell;
+        else if (L.col0)
+            u.left = (const char *)L.col0 + (size_t)r0 * kCell;
+        u.dirs = (uint8_t *)L.dirs;
+        s = run_tile(rec, prec, cp, g.blk, (const char *)b.rowsA + r0 * rb, (const char *)b.rowsB + c0 * rb,
+                     r1 - r0, c1 - c0, b, u, b.tmp, st);
+        if (s != TWED_OK) return s;
+        TRY(launch_walk((const uint8_t *)L.dirs, r0, c0, g.blk.K, (r1 - r0) + 64, L.st, path, cap, finite_edges(rec),
+                        st),
+            "walk");
+    }
+    TRY(launch_order(L.st, path, path_len, cap, st), "path order");
+#undef TRY
+    return TWED_OK;
+}
+
+// The recurrence of a twed_dp kind, or -1.
+int rec_of(int32_t kind)
+{
+    switch (kind) {
+    case TWED_DP_DTW: return kRecDtw;
+    case TWED_DP_EDIT: return kRecEdit;
+    case TWED_DP_LCS: return kRecIndel;
+    default: return -1;
+    }
+}
+
+twed_status check_dp(int32_t kind, const twed_params *prm, Prec *prec)
+{
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    if (rec_of(kind) < 0) return fail(TWED_ERR_INVALID, "unknown twed_dp_kind");
+    if (kind != TWED_DP_DTW && prm->dim != 1)
+        return fail(TWED_ERR_UNSUPPORTED, "edit distance and LCS compare 1-D samples (dim = 1)");
+    if (!(prm->strip_k == 0 || prm->strip_k == 1 || prm->strip_k == 8))
+        return fail(TWED_ERR_UNSUPPORTED, "twed_dp takes strip_k 0, 1 or 8");
+    if (!tile_prec(prm, prec)) return fail(TWED_ERR_UNSUPPORTED, "twed_dp takes TWED_F64 or TWED_F32_ACC64");
+    return TWED_OK;
 }
 
 }  // namespace
@@ -222,8 +344,8 @@ twed_status twed_pair_tile(const void *A, const void *TA, int64_t nA, const void
     t.bottom = bottom;
     t.right = right;
     t.dummy = b.dummy;
-    return run_tile(prec, cp, tile_sweep(prm->strip_k, nBt, prec, cp), b.rowsA, b.rowsB, nAt, nBt, b, t,
-                    corner ? (void *)corner : b.tmp, st);
+    return run_tile(kRecTwed, prec, cp, tile_sweep(kRecTwed, prm->strip_k, nBt, prec, cp), b.rowsA, b.rowsB, nAt,
+                    nBt, b, t, corner ? (void *)corner : b.tmp, st);
 }
 
 size_t twed_pair_path_workspace_size(int64_t nA, int64_t nB, const twed_params *prm, int64_t block)
@@ -232,8 +354,8 @@ size_t twed_pair_path_workspace_size(int64_t nA, int64_t nB, const twed_params *
     if (nA < 1 || nB < 1 || nA > kMaxLen || nB > kMaxLen || block < 0) return 0;
     if (check_params(prm) != TWED_OK || !tile_prec(prm, &prec)) return 0;
     const CostParams cp = cost_params(prm);
-    const PathGeometry g = path_geometry(prm, nA, nB, block, prec, cp);
-    return path_layout(nullptr, prm, nA, nB, g, prec).total;
+    const PathGeometry g = path_geometry(kRecTwed, prm, nA, nB, block, prec, cp);
+    return path_layout(nullptr, kRecTwed, prm, nA, nB, g, prec).total;
 }
 
 twed_status twed_pair_path(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
@@ -248,58 +370,88 @@ twed_status twed_pair_path(const void *A, const void *TA, int64_t nA, const void
     if (block < 0) return fail(TWED_ERR_INVALID, "block must be >= 0");
     Prec prec;
     if (!tile_prec(prm, &prec)) return fail(TWED_ERR_UNSUPPORTED, "the path takes TWED_F64 or TWED_F32_ACC64");
+    return path_impl(kRecTwed, A, TA, nA, B, TB, nB, prm, block, out, path, path_len, workspace, ws_bytes, prec, st);
+}
+
+size_t twed_dp_workspace_size(int32_t kind, int64_t nA, int64_t nB, const twed_params *prm)
+{
+    Prec prec;
+    if (nA < 1 || nB < 1 || nA > kMaxLen || nB > kMaxLen) return 0;
+    if (check_dp(kind, prm, &prec) != TWED_OK) return 0;
+    Carver c{nullptr};
+    SweepBuffers b{};
+    take_sweep(c, b, prec, dimt_for(prm->dim), nA, nB);
+    c.take((size_t)(nA + nB + 2) * kCell);
+    return c.used;
+}
+
+twed_status twed_dp(int32_t kind, const void *A, int64_t nA, const void *B, int64_t nB, const twed_params *prm,
+                    double *out, void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    last_error().clear();
+    Prec prec;
+    twed_status s = check_dp(kind, prm, &prec);
+    if (s != TWED_OK) return s;
+    if (!A || !B || !out) return fail(TWED_ERR_INVALID, "NULL array argument");
+    if (nA < 1 || nB < 1) return fail(TWED_ERR_INVALID, "series lengths must be >= 1");
+    if (nA > kMaxLen || nB > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    if ((s = check_workspace(workspace, ws_bytes, twed_dp_workspace_size(kind, nA, nB, prm))) != TWED_OK) return s;
+    const int rec = rec_of(kind);
+    Carver c{(char *)workspace};
+    SweepBuffers b{};
+    take_sweep(c, b, prec, dimt_for(prm->dim), nA, nB);
+    void *row0 = c.take((size_t)(nB + 1) * kCell);
+    void *col0 = c.take((size_t)(nA + 1) * kCell);
     const CostParams cp = cost_params(prm);
-    const PathGeometry g = path_geometry(prm, nA, nB, block, prec, cp);
-    if (g.H > 0x40000000LL || g.Wc > 0x40000000LL) return fail(TWED_ERR_UNSUPPORTED, "block too large");
-    if ((s = check_workspace(workspace, ws_bytes, path_layout(nullptr, prm, nA, nB, g, prec).total)) != TWED_OK)
-        return s;
-    const PathLayout L = path_layout((char *)workspace, prm, nA, nB, g, prec);
-    const SweepBuffers &b = L.b;
-    hipError_t e;
-#define TRY(call, what)                                \
-    do {                                               \
-        e = (call);                                    \
-        if (e != hipSuccess) return fail_hip(e, what); \
-    } while (0)
-    // forward sweep of the whole pair, keeping checkpoint rows and columns
-    TRY(launch_stage(prec, cp, A, TA, nullptr, 1, nA, nA, nA + 1, b.rowsA, b.flags, b.zero_words, st), "staging");
-    TRY(launch_stage(prec, cp, B, TB, nullptr, 1, nB, nB, nB + 1, b.rowsB, nullptr, 0, st), "staging");
+    hipError_t e = launch_stage(prec, cp, A, nullptr, nullptr, 1, nA, nA, nA + 1, b.rowsA, b.flags, b.zero_words, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    e = launch_stage(prec, cp, B, nullptr, nullptr, 1, nB, nB, nB + 1, b.rowsB, nullptr, 0, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
     TileArgs t{};
     t.dummy = b.dummy;
-    t.ckrow = g.nr > 0 ? L.ckrow : nullptr;
-    t.ckcol = g.nc > 0 ? L.ckcol : nullptr;
-    t.ck_rows = (int)g.H;
-    t.ck_cols = (int)g.Wc;
-    s = run_tile(prec, cp, g.fwd, b.rowsA, b.rowsB, nA, nB, b, t, out, st);
-    if (s != TWED_OK) return s;
-    // backwards, block by block: sweep the block again recording moves, walk it
-    const int64_t cap = nA + nB + 1;
-    TRY(launch_walk_init(L.st, nA, nB, st), "walk set-up");
-    const size_t rb = row_bytes(prec, dimt_for(prm->dim));
-    int64_t hst[4] = {0, 0, 0, 0};
-    const int64_t max_blocks = g.nr + g.nc + 3;
-    for (int64_t it = 0;; ++it) {
-        TRY(hipMemcpyAsync(hst, L.st, sizeof(hst), hipMemcpyDeviceToHost, st), "walk state read");
-        TRY(hipStreamSynchronize(st), "walk state read");
-        if (hst[3] == 1) break;
-        if (hst[3] != 0 || it > max_blocks || hst[0] < 1 || hst[1] < 1)
-            return fail(TWED_ERR_DEVICE, "the path could not be followed (non-finite distance or a timed-out sweep)");
-        const int64_t br = (hst[0] - 1) / g.H, bc = (hst[1] - 1) / g.Wc;
-        const int64_t r0 = br * g.H, r1 = std::min(r0 + g.H, nA);
-        const int64_t c0 = bc * g.Wc, c1 = std::min(c0 + g.Wc, nB);
-        TRY(launch_zero32(b.flags, b.zero_words, st), "flag reset");
-        TileArgs u{};
-        u.dummy = b.dummy;
-        u.top = br > 0 ? (const char *)L.ckrow + ((size_t)(br - 1) * (size_t)(nB + 1) + (size_t)c0) * kCell : nullptr;
-        u.left = bc > 0 ? (const char *)L.ckcol + ((size_t)(bc - 1) * (size_t)(nA + 1) + (size_t)r0) * kCell : nullptr;
-        u.dirs = (uint8_t *)L.dirs;
-        s = run_tile(prec, cp, g.blk, (const char *)b.rowsA + r0 * rb, (const char *)b.rowsB + c0 * rb, r1 - r0,
-                     c1 - c0, b, u, b.tmp, st);
-        if (s != TWED_OK) return s;
-        TRY(launch_walk((const uint8_t *)L.dirs, r0, c0, g.blk.K, (r1 - r0) + 64, L.st, path, cap, st), "walk");
+    if (finite_edges(rec)) {
+        if ((e = launch_index_cells(row0, nB, st)) != hipSuccess) return fail_hip(e, "boundary");
+        if ((e = launch_index_cells(col0, nA, st)) != hipSuccess) return fail_hip(e, "boundary");
+        t.top = row0;
+        t.left = col0;
     }
-    TRY(launch_order(L.st, path, path_len, cap, st), "path order");
-#undef TRY
+    s = run_tile(rec, prec, cp, tile_sweep(rec, prm->strip_k, nB, prec, cp), b.rowsA, b.rowsB, nA, nB, b, t, out, st);
+    if (s != TWED_OK) return s;
+    if (kind == TWED_DP_LCS && (e = launch_lcs_finish(out, nA, nB, st)) != hipSuccess) return fail_hip(e, "LCS");
+    return TWED_OK;
+}
+
+size_t twed_dp_path_workspace_size(int32_t kind, int64_t nA, int64_t nB, const twed_params *prm, int64_t block)
+{
+    Prec prec;
+    if (nA < 1 || nB < 1 || nA > kMaxLen || nB > kMaxLen || block < 0) return 0;
+    if (check_dp(kind, prm, &prec) != TWED_OK) return 0;
+    const int rec = rec_of(kind);
+    const CostParams cp = cost_params(prm);
+    const PathGeometry g = path_geometry(rec, prm, nA, nB, block, prec, cp);
+    return path_layout(nullptr, rec, prm, nA, nB, g, prec).total;
+}
+
+twed_status twed_dp_path(int32_t kind, const void *A, int64_t nA, const void *B, int64_t nB, const twed_params *prm,
+                         int64_t block, double *out, int64_t *path, int64_t *path_len, void *workspace,
+                         size_t ws_bytes, hipStream_t st)
+{
+    last_error().clear();
+    Prec prec;
+    twed_status s = check_dp(kind, prm, &prec);
+    if (s != TWED_OK) return s;
+    if (!A || !B) return fail(TWED_ERR_INVALID, "NULL array argument");
+    if (nA < 1 || nB < 1) return fail(TWED_ERR_INVALID, "series lengths must be >= 1");
+    if (nA > kMaxLen || nB > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    if (!out || !path || !path_len) return fail(TWED_ERR_INVALID, "NULL output argument");
+    if (block < 0) return fail(TWED_ERR_INVALID, "block must be >= 0");
+    s = path_impl(rec_of(kind), A, nullptr, nA, B, nullptr, nB, prm, block, out, path, path_len, workspace, ws_bytes,
+                  prec, st);
+    if (s != TWED_OK) return s;
+    if (kind == TWED_DP_LCS) {
+        const hipError_t e = launch_lcs_finish(out, nA, nB, st);
+        if (e != hipSuccess) return fail_hip(e, "LCS");
+    }
     return TWED_OK;
 }
 

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "twed_kernels.h"
+
 namespace twed {
 
 constexpr int kWave = 64;
@@ -236,6 +238,51 @@ __device__ __forceinline__ uint64_t lane_row_dirs(Lane<CT, AT, DIMT, K> &L, cons
         diag = L.xp[j];
         L.xp[j] = v + e;
         L.up[j] = v;
+        left = v;
+    }
+    xlast = L.xp[K - 1];
+    return code;
+}
+
+// ---- sibling recurrences ----------------------------------------------------------
+//
+// Section "Generalized Dynamic Programming Extensions" (its "Direct
+// Extension: LCS") notes that any program whose cells need only the cells
+// above, to the left and up-left can be swept the same way.  The strip sweep
+// runs three more of them over the same staged rows (timestamps and deletion
+// costs unused):
+//   DTW    D(r, c) = d(A_r, B_c) + min(D(r-1, c), D(r, c-1), D(r-1, c-1))
+//   edit   E(r, c) = min(E(r-1, c) + 1, E(r, c-1) + 1, E(r-1, c-1) + [A_r != B_c])
+//   indel  I(r, c) = min(I(r-1, c) + 1, I(r, c-1) + 1, A_r == B_c ? I(r-1, c-1) : inf)
+// The indel distance is nA + nB - 2 * LCS(A, B), so the LCS length follows
+// from it.  For these the X value a cell hands on is its DP value itself.
+// (The Rec enum is in twed_kernels.h.)
+
+template <typename CT, typename AT, int DIMT, int PM, int K, int REC, bool DIRS>
+__device__ __forceinline__ uint64_t lane_row_sibling(Lane<CT, AT, DIMT, K> &L, const Row<CT, DIMT> &a, AT &left,
+                                                     AT diag, AT &xlast, CT p, CT invp)
+{
+    static_assert(REC != kRecTwed && K <= 8, "sibling recurrences only");
+    uint64_t code = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const AT up = L.up[j];
+        AT v;
+        uint64_t mv = 0;
+        if constexpr (REC == kRecDtw) {
+            const AT d = (AT)point_dist<DIMT, PM, CT>(a.x, L.bx[j], p, invp);
+            v = d + dmin(dmin(diag, up), left);
+            if constexpr (DIRS) mv = (diag <= up && diag <= left) ? 0u : (up <= left ? 1u : 2u);
+        } else {
+            const AT sub = a.x[0] == L.bx[j][0] ? AT(0) : (REC == kRecEdit ? AT(1) : pinf<AT>());
+            const AT m = diag + sub, u = up + AT(1), l = left + AT(1);
+            v = dmin(dmin(m, u), l);
+            if constexpr (DIRS) mv = (m <= u && m <= l) ? 0u : (u <= l ? 1u : 2u);
+        }
+        if constexpr (DIRS) code |= mv << (8 * j);
+        diag = up;
+        L.up[j] = v;
+        L.xp[j] = v;
         left = v;
     }
     xlast = L.xp[K - 1];

@@ -10,6 +10,10 @@ namespace twed {
 // Precision of one launch (resolved: no AUTO here).
 enum Prec : int { kF64 = 0, kF32 = 1, kF32Acc64 = 2 };
 
+// Recurrence of a strip sweep: TWED, or one of its siblings (dynamic time
+// warping, edit distance, indel distance; lane_row_sibling in twed_device.h).
+enum Rec : int { kRecTwed = 0, kRecDtw = 1, kRecEdit = 2, kRecIndel = 3 };
+
 // Sample dimensions the kernels are compiled for; a call with dim d runs the
 // smallest compiled DIMT >= d with the extra components zero.
 int dimt_for(int dim);
@@ -41,6 +45,7 @@ inline size_t rows_bytes(Prec prec, int dimt, int64_t rows)
 // 32-bit words at `zero_ptr` (may be null).  With first_prev (a single
 // series only) X and T start one sample into a longer series: the deletion
 // cost of row 1 is taken against the sample before X[0] instead of the pad.
+// T may be null (every timestamp 0: the sibling recurrences use none).
 hipError_t launch_stage(Prec prec, const CostParams &cp, const void *X, const void *T,
                         const int64_t *off, int64_t nSeries, int64_t n_single, int64_t max_len,
                         int64_t total_rows, void *rows, uint32_t *zero_ptr, int64_t zero_words, hipStream_t st,
@@ -92,6 +97,17 @@ hipError_t launch_tile(Prec prec, const CostParams &cp, int K, const WavefrontAr
                        hipStream_t st);
 size_t tile_scratch_bytes(Prec prec, const CostParams &cp, int K, int G);
 int tile_max_workers(Prec prec, const CostParams &cp, int K, int G);
+// Column 0 of the output rows and row 0 of the output columns (copied from
+// the inputs or set to the +inf pad); launched after every tile sweep.
+hipError_t launch_tile_edges(int64_t nA, int64_t nB, const TileArgs &t, hipStream_t st);
+// The tile sweep on a sibling recurrence (dp.hip; rec: 1 DTW, 2 edit
+// distance, 3 indel distance), strips of K = 1 or 8 columns per lane, groups
+// of G = 1 or 8 strips; other configurations return hipErrorInvalidValue /
+// (size_t)-1 / 0.
+hipError_t launch_dp(int rec, Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, const TileArgs &t,
+                     hipStream_t st);
+size_t dp_scratch_bytes(int rec, Prec prec, const CostParams &cp, int K, int G);
+int dp_max_workers(int rec, Prec prec, const CostParams &cp, int K, int G);
 
 // Path read-back (path.hip).  st holds {r, c, cells written, status}.
 hipError_t launch_walk_init(int64_t *st, int64_t nA, int64_t nB, hipStream_t s);
@@ -99,7 +115,11 @@ hipError_t launch_walk_init(int64_t *st, int64_t nA, int64_t nB, hipStream_t s);
 // column c0 (dirs in the tile sweep's order with strip width 64*K and T =
 // block rows + 64 steps per strip) until the walk leaves the block.
 hipError_t launch_walk(const uint8_t *dirs, int64_t r0, int64_t c0, int K, int64_t T, int64_t *st, int64_t *rev,
-                       int64_t cap, hipStream_t s);
+                       int64_t cap, bool free_edges, hipStream_t s);
+// n + 1 (DP, X) cells (i, i), i = 0..n: the boundary of edit / indel distances.
+hipError_t launch_index_cells(void *cells, int64_t n, hipStream_t s);
+// out[0] = (nA + nB - out[0]) / 2: the LCS length from the indel distance.
+hipError_t launch_lcs_finish(double *out, int64_t nA, int64_t nB, hipStream_t s);
 // Zeroes n 32-bit words (a kernel, so that it can be captured in a graph).
 hipError_t launch_zero32(uint32_t *p, int64_t n, hipStream_t s);
 // Reverses the st[2] cells of `path` in place and writes the count to len.

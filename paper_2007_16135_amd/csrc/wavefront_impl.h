@@ -136,12 +136,13 @@ constexpr bool kStripCompiled = DIMT <= 16 || K <= 2;
 // first real row; in a pair sweep those rows keep the +inf state of the pad
 // row, and in a tile the lane loads its top-row cells at the step where it
 // sits on row 0, so that row 1 starts from them.
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC>
 __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g, int s, const CT *__restrict__ rowsA,
                                             const CT *__restrict__ rowsB, int nA, int nB, const CostArgs<CT> &ca,
                                             Pair2<AT> *bnd, uint32_t *flags, uint32_t *err, int nStrips, CT beta,
                                             AT *out, AT *dump, int sub_shift, const TileIO<AT> &io)
 {
+    static_assert(REC == kRecTwed || TILE, "sibling recurrences run as tiles");
     const int kSub = 1 << sub_shift;
     constexpr int S = Row<CT, DIMT>::kStride;
     constexpr int W = kWave * K;
@@ -251,11 +252,19 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
             AT left = sh_l, xl;
             if constexpr (TILE) {
                 if (io.dirs != nullptr) {
-                    const uint64_t code = lane_row_dirs<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p,
-                                                                             ca.invp);
+                    uint64_t code;
+                    if constexpr (REC == kRecTwed)
+                        code = lane_row_dirs<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p, ca.invp);
+                    else
+                        code = lane_row_sibling<CT, AT, DIMT, PM, K, REC, true>(L, use, left, sh_xo, xl, ca.p,
+                                                                                ca.invp);
                     store_dirs<K>(io.dirs + (((size_t)s * (size_t)T + (size_t)t) * kWave + lane) * K, code);
                 } else {
-                    lane_row<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p, ca.invp, beta);
+                    if constexpr (REC == kRecTwed)
+                        lane_row<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p, ca.invp, beta);
+                    else
+                        (void)lane_row_sibling<CT, AT, DIMT, PM, K, REC, false>(L, use, left, sh_xo, xl, ca.p,
+                                                                                ca.invp);
                 }
                 // the lane sits on row 0: its top-row cells replace the pad state
                 if (io.top != nullptr && t < kWave) {
@@ -399,7 +408,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
 // Two global slots suffice: group g+2 writes row r of its boundary only
 // after group g+1 has read row r from the slot both use (it reads a row
 // before its own last wave can produce that row).
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC = kRecTwed>
 __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restrict__ rowsA,
                                                              const CT *__restrict__ rowsB, int nA, int nB,
                                                              CostArgs<CT> ca, Pair2<AT> *bnd, uint32_t *flags,
@@ -426,26 +435,26 @@ __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restri
         if (g >= nGroups) break;
         const int s = g * G + w;
         if (s < nStrips)
-            sweep_strip<CT, AT, DIMT, PM, K, G, DUMP, TILE>(sh, w, g, s, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
+            sweep_strip<CT, AT, DIMT, PM, K, G, DUMP, TILE, REC>(sh, w, g, s, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
                                                             nStrips, beta, out, dump, sub_shift, io);
     }
 }
 
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE, int REC = kRecTwed>
 int occupancy_kg()
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE, REC>,
                                                      kWave * G, 0) != hipSuccess)
         return 0;
     return blocks;
 }
 
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE, int REC = kRecTwed>
 size_t scratch_kg()
 {
     hipFuncAttributes attr{};
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE>)) !=
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE, REC>)) !=
         hipSuccess)
         return (size_t)-1;
     return attr.localSizeBytes;

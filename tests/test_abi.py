@@ -258,3 +258,26 @@ def test_tile_and_path_host_checks(L):
     assert path(pth=None) == INVALID
     assert path(p=tw.make_params(dim=2, precision="f32")) == UNSUPPORTED
     assert path() == WORKSPACE
+
+
+def test_dp_host_checks(L):
+    c = ctypes
+    prm1 = tw.make_params(dim=1)
+    assert L.twed_dp_workspace_size(2, 100, 90, c.byref(prm1)) > 0
+    assert L.twed_dp_workspace_size(9, 100, 90, c.byref(prm1)) == 0          # unknown kind
+    assert L.twed_dp_workspace_size(2, 100, 90, c.byref(tw.make_params(dim=3))) == 0   # edit needs dim 1
+    assert L.twed_dp_workspace_size(1, 100, 90, c.byref(tw.make_params(dim=3))) > 0    # DTW in 3-D
+
+    def dp(kind, p=prm1, A=FAKE, out=FAKE, n=10):
+        return L.twed_dp(kind, A, n, FAKE, n, c.byref(p), out, None, 0, None)
+
+    assert dp(0) == INVALID
+    assert dp(2, A=None) == INVALID
+    assert dp(2, out=None) == INVALID
+    assert dp(2, n=0) == INVALID
+    assert dp(3, p=tw.make_params(dim=2)) == UNSUPPORTED
+    assert dp(1, p=tw.make_params(precision="f32")) == UNSUPPORTED
+    assert dp(1, p=tw.make_params(strip_k=2)) == UNSUPPORTED
+    assert dp(1) == WORKSPACE
+    assert L.twed_dp_path(2, FAKE, 10, FAKE, 10, c.byref(prm1), -1, FAKE, FAKE, FAKE, None, 0, None) == INVALID
+    assert L.twed_dp_path(2, FAKE, 10, FAKE, 10, c.byref(prm1), 0, FAKE, None, FAKE, None, 0, None) == INVALID
