@@ -325,6 +325,31 @@ def main():
             "forward_GCUPS_equiv": round(float(pn) * pn / (pwall / 2) / 1e9, 3)}
         log(f"path: {result['alignment_path']}")
 
+    # ---- sibling programs on the band sweep: LCS of 1e6-token sequences, 8-D DTW
+    if not args.no_tiles:
+        rng = np.random.default_rng(7)
+        la = torch.as_tensor(rng.integers(0, 4, n).astype(np.float32), device=dev)
+        lb = torch.as_tensor(rng.integers(0, 4, n).astype(np.float32), device=dev)
+        lws = torch.empty(max(tw.binding.twed_dp_workspace_size("lcs", n, n,
+                                                               tw.make_params(0.0, 0.0, 1.0, 1, "f32_acc64")), 256),
+                          dtype=torch.uint8, device=dev)
+        lwall, lper = time_steps(lambda: tw.twed_dp("lcs", la, lb, precision="f32_acc64", workspace=lws), 2, 1,
+                                 torch)
+        lk = float(np.mean(lper))
+        dn = min(n, 250_000)
+        dA, dB = A[:dn].contiguous(), B[:dn].contiguous()
+        dwall, dper = time_steps(lambda: tw.twed_dp("dtw", dA, dB, p=2.0, precision="f32_acc64"), 2, 1, torch)
+        dk = float(np.mean(dper))
+        result["siblings"] = {
+            "lcs": {"workload": f"LCS length of two {n}-token sequences (alphabet of 4, seed 7), FP32 tokens, "
+                                f"FP64 accumulators", "ms": round(lk * 1e3, 3),
+                    "GCUPS": round(float(n) * n / lk / 1e9, 3)},
+            "dtw": {"workload": f"DTW of the first {dn} samples of the headline pair (8-D, L2), FP32 costs, "
+                                f"FP64 accumulators", "ms": round(dk * 1e3, 3),
+                    "GCUPS": round(float(dn) * dn / dk / 1e9, 3)},
+        }
+        log(f"siblings: {result['siblings']}")
+
     # ---- R^28: one query against 60,000 series of 28 samples in R^28 (FP64, L2)
     if not args.no_rn:
         log("generating 60000 x 28 series in R^28")

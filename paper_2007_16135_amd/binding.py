@@ -274,6 +274,11 @@ def twed_pair_tile(A, TA, B, TB, r0, r1, c0, c1, top=None, left=None, nu=1e-3, l
     return corner, bot, rig
 
 
+def twed_dp_workspace_size(kind, nA, nB, prm: TwedParams) -> int:
+    k = DP_KINDS[kind] if isinstance(kind, str) else int(kind)
+    return load_library().twed_dp_workspace_size(k, int(nA), int(nB), ctypes.byref(prm))
+
+
 def twed_pair_path_workspace_size(nA, nB, prm: TwedParams, block=0) -> int:
     return load_library().twed_pair_path_workspace_size(int(nA), int(nB), ctypes.byref(prm), int(block))
 
