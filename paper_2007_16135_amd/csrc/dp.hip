@@ -77,6 +77,7 @@ hipError_t by_config(int rec, Prec prec, const CostParams &cp, int K, int G, Fn 
 hipError_t launch_dp(int rec, Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, const TileArgs &t,
                      hipStream_t st)
 {
+    if (t.dirs) return launch_rec_dirs(rec, prec, cp, K, a, t, st);
     hipError_t e = by_config(rec, prec, cp, K, a.group,
                              [&]<typename CT, typename AT, int DIMT, int PM, int KK, int G, int REC>() -> hipError_t {
                                  TileIO<AT> io{};

@@ -13,15 +13,23 @@ namespace twed {
 
 namespace {
 
-// One thread: the walk is a chain of dependent loads.  st = {r, c, n, status}
+// One wave.  The walk is a chain of dependent reads, so the moves of the 64 x
+// 64 cells up and to the left of the current cell are first gathered into
+// LDS (lane l reads one column, 64 rows: every row of a column sits 64*K
+// bytes after the previous one in sweep order), and the walk then follows
+// them there until it leaves that window.  Every lane runs the same walk
+// (uniform control flow) and stores the same cells.  st = {r, c, n, status}
 // in global coordinates; status 0 running, 1 reached (0, 0), -1 failed.
+//
 // With free_edges (edit and indel distances, whose row 0 and column 0 are
 // finite) a walk that reaches row 0 or column 0 follows it to (0, 0); for
 // TWED and DTW those cells are +inf and reaching one is an error.
-__global__ void walk_kernel(const uint8_t *__restrict__ dirs, int64_t r0, int64_t c0, int K, int64_t T,
-                            int64_t *st, int64_t *rev, int64_t cap, int free_edges)
+__global__ __launch_bounds__(kWave) void walk_kernel(const uint8_t *__restrict__ dirs, int64_t r0, int64_t c0,
+                                                     int64_t nAt, int64_t nBt, int K, int64_t T, int64_t *st,
+                                                     int64_t *rev, int64_t cap, int free_edges)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    __shared__ uint8_t win[kWave * kWave];
+    const int lane = threadIdx.x;
     if (st[3] != 0) return;
     int64_t r = st[0], c = st[1], n = st[2];
     int64_t status = 0;
@@ -40,34 +48,52 @@ __global__ void walk_kernel(const uint8_t *__restrict__ dirs, int64_t r0, int64_
                 if (r > 0) --r;
                 else --c;
             }
-            status = (r == 0 && c == 0 && n <= cap) ? 1 : -1;
+            status = (r == 0 && c == 0) ? 1 : -1;
             break;
         }
         const int64_t rr = r - r0, cc = c - c0;
         if (rr <= 0 || cc <= 0) break;  // the cell belongs to the block above or to the left
-        if (n >= cap) {
-            status = -1;
-            break;
+        // window of local rows wr..rr and columns wc..cc
+        const int64_t wr = rr - (kWave - 1), wc = cc - (kWave - 1);
+        __syncthreads();  // the previous window has been read
+        {
+            int64_t col = wc + lane;
+            col = col < 1 ? 1 : (col > nBt ? nBt : col);
+            const int64_t s = (col - 1) / W, within = (col - 1) - s * W;
+            const int64_t ln = within / K, j = within - ln * K;
+            for (int k = 0; k < kWave; ++k) {
+                int64_t row = wr + k;
+                row = row < 1 ? 1 : (row > nAt ? nAt : row);
+                win[k * kWave + lane] = dirs[((s * T + row + ln) * kWave + ln) * K + j];
+            }
         }
-        rev[2 * n] = r;
-        rev[2 * n + 1] = c;
-        ++n;
-        const int64_t s = (cc - 1) / W, within = (cc - 1) - s * W;
-        const int64_t lane = within / K, j = within - lane * K;
-        const uint8_t mv = dirs[((s * T + rr + lane) * kWave + lane) * K + j];
-        if (mv == 0) {
-            --r;
-            --c;
-        } else if (mv == 1) {
-            --r;
-        } else if (mv == 2) {
-            --c;
-        } else {
-            status = -1;
-            break;
+        __syncthreads();
+        for (;;) {
+            const int64_t lr = r - r0, lc = c - c0;
+            if (r == 0 || c == 0 || lr <= 0 || lc <= 0 || lr < wr || lc < wc) break;
+            if (n >= cap) {
+                status = -1;
+                break;
+            }
+            rev[2 * n] = r;
+            rev[2 * n + 1] = c;
+            ++n;
+            const uint8_t mv = win[(lr - wr) * kWave + (lc - wc)];
+            if (mv == 0) {
+                --r;
+                --c;
+            } else if (mv == 1) {
+                --r;
+            } else if (mv == 2) {
+                --c;
+            } else {
+                status = -1;
+                break;
+            }
         }
+        if (status != 0) break;
     }
-    st[0] = r;
+    st[0] = r;  // every lane stores the same values
     st[1] = c;
     st[2] = n;
     st[3] = status;
@@ -106,10 +132,11 @@ hipError_t launch_walk_init(int64_t *st, int64_t nA, int64_t nB, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_walk(const uint8_t *dirs, int64_t r0, int64_t c0, int K, int64_t T, int64_t *st, int64_t *rev,
-                       int64_t cap, bool free_edges, hipStream_t s)
+hipError_t launch_walk(const uint8_t *dirs, int64_t r0, int64_t c0, int64_t nAt, int64_t nBt, int K, int64_t T,
+                       int64_t *st, int64_t *rev, int64_t cap, bool free_edges, hipStream_t s)
 {
-    hipLaunchKernelGGL(walk_kernel, dim3(1), dim3(1), 0, s, dirs, r0, c0, K, T, st, rev, cap, free_edges ? 1 : 0);
+    hipLaunchKernelGGL(walk_kernel, dim3(1), dim3(kWave), 0, s, dirs, r0, c0, nAt, nBt, K, T, st, rev, cap,
+                       free_edges ? 1 : 0);
     return hipGetLastError();
 }
 

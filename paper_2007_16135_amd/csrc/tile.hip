@@ -91,6 +91,7 @@ hipError_t launch_tile(Prec prec, const CostParams &cp, int K, const WavefrontAr
                        hipStream_t st)
 {
     if (prec != kF64 && prec != kF32Acc64) return hipErrorInvalidValue;
+    if (t.dirs) return launch_tile_dirs(prec, cp, K, a, t, st);
     hipError_t e = by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
         if constexpr (!std::is_same_v<AT, double>) {
             return hipErrorInvalidValue;

@@ -51,23 +51,33 @@ struct Sweep {
 // The recurrence a sweep runs: kRecTwed, or a sibling (kRecDtw, kRecEdit,
 // kRecIndel; see twed_device.h), whose kernels exist for K in {1, 8} and G
 // in {1, 8} only.
-size_t sweep_scratch(int rec, Prec prec, const CostParams &cp, int K, int G)
+size_t sweep_scratch(int rec, bool dirs, Prec prec, const CostParams &cp, int K, int G)
 {
+    if (dirs) return rec_dirs_scratch_bytes(rec, prec, cp, K, G);
     return rec == kRecTwed ? tile_scratch_bytes(prec, cp, K, G) : dp_scratch_bytes(rec, prec, cp, K, G);
 }
 
-Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &cp)
+int sweep_workers(int rec, bool dirs, Prec prec, const CostParams &cp, int K, int G)
 {
-    const bool sib = rec != kRecTwed;
+    if (dirs) return rec_dirs_max_workers(rec, prec, cp, K, G);
+    return rec == kRecTwed ? tile_max_workers(prec, cp, K, G) : dp_max_workers(rec, prec, cp, K, G);
+}
+
+// Move-recording sweeps (dirs) run strips of one column per lane.
+Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &cp, bool dirs = false)
+{
+    const bool sib = rec != kRecTwed && !dirs;
     int K = 1;
-    if (strip_k > 0) {
+    if (dirs) {
+        K = 1;
+    } else if (strip_k > 0) {
         K = strip_k;
     } else {
         const int64_t want = (int64_t)simds() * 3 / 2;
         for (int k : {8, 4, 2}) {
             if (sib && k != 8) continue;
             const int64_t strips = (nB + 64 * k - 1) / (64 * k);
-            if (strips >= want && sweep_scratch(rec, prec, cp, k, 1) == 0) {
+            if (strips >= want && sweep_scratch(rec, dirs, prec, cp, k, 1) == 0) {
                 K = k;
                 break;
             }
@@ -78,7 +88,7 @@ Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &
     int G = 1;
     for (int g : {8, 4}) {
         if (sib && g != 8) continue;
-        if (nStrips * 10 >= (int64_t)g * cus * 9 && sweep_scratch(rec, prec, cp, K, g) == 0) {
+        if (nStrips * 10 >= (int64_t)g * cus * 9 && sweep_scratch(rec, dirs, prec, cp, K, g) == 0) {
             G = g;
             break;
         }
@@ -121,8 +131,7 @@ twed_status run_tile(int rec, Prec prec, const CostParams &cp, Sweep sw, const v
     w.dump = nullptr;
     w.group = sw.G;
     w.sub_shift = 4;
-    const int workers = rec == kRecTwed ? tile_max_workers(prec, cp, sw.K, sw.G)
-                                        : dp_max_workers(rec, prec, cp, sw.K, sw.G);
+    const int workers = sweep_workers(rec, t.dirs != nullptr, prec, cp, sw.K, sw.G);
     if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
     w.grid = (int)std::min<int64_t>((w.nStrips + sw.G - 1) / sw.G, workers);
     const hipError_t e = rec == kRecTwed ? launch_tile(prec, cp, sw.K, w, t, st)
@@ -159,7 +168,7 @@ PathGeometry path_geometry(int rec, const twed_params *prm, int64_t nA, int64_t 
     g.Wc = (std::max(want, W) + W - 1) / W * W;
     g.nr = (nA - 1) / g.H;
     g.nc = (nB - 1) / g.Wc;
-    g.blk = tile_sweep(rec, 0, std::min(g.Wc, nB), prec, cp);
+    g.blk = tile_sweep(rec, 0, std::min(g.Wc, nB), prec, cp, true);
     return g;
 }
 
@@ -260,8 +269,8 @@ twed_status path_impl(int rec, const void *A, const void *TA, int64_t nA, const 
         s = run_tile(rec, prec, cp, g.blk, (const char *)b.rowsA + r0 * rb, (const char *)b.rowsB + c0 * rb,
                      r1 - r0, c1 - c0, b, u, b.tmp, st);
         if (s != TWED_OK) return s;
-        TRY(launch_walk((const uint8_t *)L.dirs, r0, c0, g.blk.K, (r1 - r0) + 64, L.st, path, cap, finite_edges(rec),
-                        st),
+        TRY(launch_walk((const uint8_t *)L.dirs, r0, c0, r1 - r0, c1 - c0, g.blk.K, (r1 - r0) + 64, L.st, path, cap,
+                        finite_edges(rec), st),
             "walk");
     }
     TRY(launch_order(L.st, path, path_len, cap, st), "path order");

@@ -87,7 +87,7 @@ struct TileArgs {
     void *ckrow;        // rows ck_rows, 2*ck_rows, ... < nA, nB + 1 cells each
     void *ckcol;        // columns ck_cols, 2*ck_cols, ... < nB, nA + 1 cells each
     void *dummy;        // 512 cells of scratch
-    uint8_t *dirs;      // moves, nStrips * (nA + 64) * 64 * K bytes
+    uint8_t *dirs;      // moves, nStrips * (nA + 64) * 64 * K bytes (recording kernels, K = 1)
     int ck_rows;        // >= 64
     int ck_cols;        // a multiple of the strip width 64*K
 };
@@ -106,16 +106,25 @@ hipError_t launch_tile_edges(int64_t nA, int64_t nB, const TileArgs &t, hipStrea
 // (size_t)-1 / 0.
 hipError_t launch_dp(int rec, Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, const TileArgs &t,
                      hipStream_t st);
+// Tile sweeps that record moves (t.dirs set; tile_dirs.hip): any recurrence,
+// K = 1 only, G = 1, 4 or 8.  launch_tile / launch_dp with t.dirs set call
+// these.
+hipError_t launch_tile_dirs(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, const TileArgs &t,
+                            hipStream_t st);
+hipError_t launch_rec_dirs(int rec, Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, const TileArgs &t,
+                           hipStream_t st);
+size_t rec_dirs_scratch_bytes(int rec, Prec prec, const CostParams &cp, int K, int G);
+int rec_dirs_max_workers(int rec, Prec prec, const CostParams &cp, int K, int G);
 size_t dp_scratch_bytes(int rec, Prec prec, const CostParams &cp, int K, int G);
 int dp_max_workers(int rec, Prec prec, const CostParams &cp, int K, int G);
 
 // Path read-back (path.hip).  st holds {r, c, cells written, status}.
 hipError_t launch_walk_init(int64_t *st, int64_t nA, int64_t nB, hipStream_t s);
-// Follows the moves of the block whose row 0 / column 0 are global row r0 /
-// column c0 (dirs in the tile sweep's order with strip width 64*K and T =
-// block rows + 64 steps per strip) until the walk leaves the block.
-hipError_t launch_walk(const uint8_t *dirs, int64_t r0, int64_t c0, int K, int64_t T, int64_t *st, int64_t *rev,
-                       int64_t cap, bool free_edges, hipStream_t s);
+// Follows the moves of the block (nAt x nBt cells) whose row 0 / column 0
+// are global row r0 / column c0 (dirs in the tile sweep's order with strip
+// width 64*K and T = nAt + 64 steps per strip) until the walk leaves it.
+hipError_t launch_walk(const uint8_t *dirs, int64_t r0, int64_t c0, int64_t nAt, int64_t nBt, int K, int64_t T,
+                       int64_t *st, int64_t *rev, int64_t cap, bool free_edges, hipStream_t s);
 // n + 1 (DP, X) cells (i, i), i = 0..n: the boundary of edit / indel distances.
 hipError_t launch_index_cells(void *cells, int64_t n, hipStream_t s);
 // out[0] = (nA + nB - out[0]) / 2: the LCS length from the indel distance.

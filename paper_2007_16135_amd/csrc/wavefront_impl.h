@@ -87,9 +87,9 @@ __device__ __forceinline__ void wait_progress(const uint32_t *p, uint32_t need, 
 //   ckcol   receives columns ck_cols, 2*ck_cols, ... left of nB (nA + 1
 //           cells each; row 0 is left to the host); ck_cols is a multiple
 //           of the strip width
-//   dirs    one byte per cell, the move into it (0 match, 1 deletion in A
-//           from the cell above, 2 deletion in B from the cell on the left),
-//           in sweep order: strip s, step t, lane, column
+//   dirs    (DIRS kernels) one byte per cell, the move into it (0 match,
+//           1 deletion in A from the cell above, 2 deletion in B from the
+//           cell on the left), in sweep order: strip s, step t, lane, column
 //   dummy   64*K cells that lanes without a cell to store write instead
 template <typename AT>
 struct TileIO {
@@ -136,13 +136,14 @@ constexpr bool kStripCompiled = DIMT <= 16 || K <= 2;
 // first real row; in a pair sweep those rows keep the +inf state of the pad
 // row, and in a tile the lane loads its top-row cells at the step where it
 // sits on row 0, so that row 1 starts from them.
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC, bool DIRS>
 __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g, int s, const CT *__restrict__ rowsA,
                                             const CT *__restrict__ rowsB, int nA, int nB, const CostArgs<CT> &ca,
                                             Pair2<AT> *bnd, uint32_t *flags, uint32_t *err, int nStrips, CT beta,
                                             AT *out, AT *dump, int sub_shift, const TileIO<AT> &io)
 {
     static_assert(REC == kRecTwed || TILE, "sibling recurrences run as tiles");
+    static_assert(!DIRS || TILE, "moves are recorded by tile sweeps");
     const int kSub = 1 << sub_shift;
     constexpr int S = Row<CT, DIMT>::kStride;
     constexpr int W = kWave * K;
@@ -251,7 +252,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
 
             AT left = sh_l, xl;
             if constexpr (TILE) {
-                if (io.dirs != nullptr) {
+                if constexpr (DIRS) {
                     uint64_t code;
                     if constexpr (REC == kRecTwed)
                         code = lane_row_dirs<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p, ca.invp);
@@ -408,7 +409,8 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
 // Two global slots suffice: group g+2 writes row r of its boundary only
 // after group g+1 has read row r from the slot both use (it reads a row
 // before its own last wave can produce that row).
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC = kRecTwed>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC = kRecTwed,
+          bool DIRS = false>
 __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restrict__ rowsA,
                                                              const CT *__restrict__ rowsB, int nA, int nB,
                                                              CostArgs<CT> ca, Pair2<AT> *bnd, uint32_t *flags,
@@ -435,26 +437,28 @@ __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restri
         if (g >= nGroups) break;
         const int s = g * G + w;
         if (s < nStrips)
-            sweep_strip<CT, AT, DIMT, PM, K, G, DUMP, TILE, REC>(sh, w, g, s, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
+            sweep_strip<CT, AT, DIMT, PM, K, G, DUMP, TILE, REC, DIRS>(sh, w, g, s, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
                                                             nStrips, beta, out, dump, sub_shift, io);
     }
 }
 
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE, int REC = kRecTwed>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE, int REC = kRecTwed,
+          bool DIRS = false>
 int occupancy_kg()
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE, REC>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE, REC, DIRS>,
                                                      kWave * G, 0) != hipSuccess)
         return 0;
     return blocks;
 }
 
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE, int REC = kRecTwed>
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE, int REC = kRecTwed,
+          bool DIRS = false>
 size_t scratch_kg()
 {
     hipFuncAttributes attr{};
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE, REC>)) !=
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(wavefront_kernel<CT, AT, DIMT, PM, K, G, false, TILE, REC, DIRS>)) !=
         hipSuccess)
         return (size_t)-1;
     return attr.localSizeBytes;
