@@ -83,12 +83,17 @@ Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &
             }
         }
     }
+    // Groups: in-group handoffs go through LDS, which shortens the pipeline,
+    // so the widest group that still leaves work for half the CUs; a
+    // move-recording sweep of one block is latency-bound, not width-bound,
+    // and takes the widest group that has a few groups to pipeline.
     const int64_t nStrips = (nB + 64 * K - 1) / (64 * K);
     const int64_t cus = std::max(1, simds() / 4);
+    const int64_t want_groups = dirs ? 2 : std::max<int64_t>(1, cus / 2);
     int G = 1;
     for (int g : {8, 4}) {
         if (sib && g != 8) continue;
-        if (nStrips * 10 >= (int64_t)g * cus * 9 && sweep_scratch(rec, dirs, prec, cp, K, g) == 0) {
+        if ((nStrips + g - 1) / g >= want_groups && nStrips >= g && sweep_scratch(rec, dirs, prec, cp, K, g) == 0) {
             G = g;
             break;
         }

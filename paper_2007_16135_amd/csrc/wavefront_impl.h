@@ -204,8 +204,19 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     }
 
     const int T = nA + kWave;  // lane 63 reaches row nA at step nA + 63
+    // Rows of A are loaded kAhead steps before their use: one step of 64*K
+    // columns hides the load behind K cells of work, which is enough for
+    // wide strips; narrow strips of small samples keep a ring of kAhead + 1
+    // rows (kAhead + 1 divides every sub-chunk of 8, 16 or 32 steps).
+    constexpr int kAhead = (K <= 2 && DIMT <= 8) ? 3 : 1;
     Row<CT, DIMT> cur, nxt;
-    load_row<CT, DIMT>(rowsA_lane, 0, cur);
+    Row<CT, DIMT> ring[kAhead + 1];
+    if constexpr (kAhead == 1) {
+        load_row<CT, DIMT>(rowsA_lane, 0, cur);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) load_row<CT, DIMT>(rowsA_lane, k, ring[k]);
+    }
     // Left boundary of the current window of 64 steps: lane l holds row
     // wb + 1 + l (DP in cdp, X in cx; two scalars, so that selecting a lane's
     // new row stays in registers).
@@ -248,7 +259,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
         // prefetched row never has to be copied.
         auto step = [&](int i, Row<CT, DIMT> &use, Row<CT, DIMT> &fill) {
             const int t = t0 + i;
-            load_row<CT, DIMT>(rowsA_lane, t + 1, fill);
+            load_row<CT, DIMT>(rowsA_lane, t + kAhead, fill);
 
             AT left = sh_l, xl;
             if constexpr (TILE) {
@@ -352,13 +363,29 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
             }
         };
         int i = 0;
-        for (; i + 1 < steps; i += 2) {
-            step(i, cur, nxt);
-            step(i + 1, nxt, cur);
-        }
-        if (i < steps) {
-            step(i, cur, nxt);
-            cur = nxt;
+        if constexpr (kAhead == 1) {
+            for (; i + 1 < steps; i += 2) {
+                step(i, cur, nxt);
+                step(i + 1, nxt, cur);
+            }
+            if (i < steps) {
+                step(i, cur, nxt);
+                cur = nxt;
+            }
+        } else {
+            // ring[k] holds row t + k (k < kAhead) at the start of each run of
+            // kAhead + 1 steps; sub-chunks are multiples of that run except
+            // at the end of the sweep, where the ring is shifted step by step
+            constexpr int R = kAhead + 1;
+            for (; i + R <= steps; i += R) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) step(i + k, ring[k], ring[(k + kAhead) % R]);
+            }
+            for (; i < steps; ++i) {
+                step(i, ring[0], ring[kAhead]);
+#pragma unroll
+                for (int k = 0; k < kAhead; ++k) ring[k] = ring[k + 1];
+            }
         }
 
         const int tend = t0 + steps;        // steps done so far
