@@ -66,7 +66,11 @@ __device__ __forceinline__ AT sweep_pair(const CT *__restrict__ rowsA, int nA, c
     // past row nA it reads a neighbouring series or the 64 zero rows that pad
     // every packed buffer (rows -63 .. nA + 64 are touched).  Those rows only
     // meet +inf operands (before row 0) or feed no result (past row nA).
-    const CT *pa = rowsA - (ptrdiff_t)lane * Row<CT, DIMT>::kStride;
+    // For wide samples, lanes whose columns all lie past nB (they feed no
+    // result: values only flow to higher lanes) read lane 0's row, which the
+    // wave's load then serves once instead of fetching rows nobody needs.
+    const int row_lane = (DIMT < 8 || c0 <= nB) ? lane : 0;
+    const CT *pa = rowsA - (ptrdiff_t)row_lane * Row<CT, DIMT>::kStride;
     Row<CT, DIMT> ra, rb;
     load_row<CT, DIMT>(pa, 0, ra);
     auto step = [&](const Row<CT, DIMT> &row) {
@@ -112,56 +116,60 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
                                                    const int32_t *__restrict__ order,
                                                    const int64_t *__restrict__ pairs, int64_t nX, int64_t nY,
                                                    int64_t nItems, int mode, CostArgs<CT> ca, AT *D,
-                                                   uint32_t *ticket)
+                                                   uint32_t *ticket, int chunk)
 {
     constexpr int S = Row<CT, DIMT>::kStride;
     constexpr int KMAX = kmax_of<DIMT>();
+    // A ticket is `chunk` consecutive items: for short pairs one atomic per
+    // pair on a single counter would cost more than the pair itself.
     for (;;) {
-        const int64_t item = (int64_t)next_ticket(ticket);
-        if (item >= nItems) break;
-
-        int64_t a, b;
-        if (mode == kSymmetric) {
-            // item -> (i < j) over the length-sorted order: j-th group holds
-            // the pairs (0..j-1, j).
-            int64_t j = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)item)) * 0.5);
-            while (j * (j - 1) / 2 > item) --j;
-            while ((j + 1) * j / 2 <= item) ++j;
-            const int64_t i = item - j * (j - 1) / 2;
-            a = order[i];
-            b = order[j];
-        } else if (mode == kRect) {
-            a = item / nY;
-            b = item - a * nY;
-        } else {
-            a = pairs[2 * item];
-            b = pairs[2 * item + 1];
-        }
-        // a pair-list entry outside the collections yields NaN (swept as (0, 0))
-        const bool ok = a >= 0 && a < nX && b >= 0 && b < nY;
-        a = ok ? a : 0;
-        b = ok ? b : 0;
-        const int64_t xa = offX[a], la = offX[a + 1] - xa;
-        const int64_t yb = offY[b], lb = offY[b + 1] - yb;
-        const CT *ra = rowsX + (xa + a) * S;
-        const CT *rb = rowsY + (yb + b) * S;
-        // shorter operand across the lanes
-        const bool swap = lb > la;
-        const CT *rowsA = swap ? rb : ra;
-        const CT *rowsB = swap ? ra : rb;
-        const int nA = (int)(swap ? lb : la);
-        const int nB = (int)(swap ? la : lb);
-        const int k = (nB + kWave - 1) / kWave;
-        // Pairs wider than one wave are swept by the single-pair path instead.
-        if (k <= KMAX) {
-            // d is the same in every lane; every lane stores it (one
-            // transaction), so the loop body holds no lane-conditional branch.
-            const AT d = sweep_dispatch<CT, AT, DIMT, PM, 1>(k, rowsA, nA, rowsB, nB, ca);
+        const int64_t first = (int64_t)next_ticket(ticket) * chunk;
+        if (first >= nItems) break;
+        const int64_t last = first + chunk < nItems ? first + chunk : nItems;
+        for (int64_t item = first; item < last; ++item) {
+            int64_t a, b;
             if (mode == kSymmetric) {
-                D[a * nX + b] = d;
-                D[b * nX + a] = d;
+                // item -> (i < j) over the length-sorted order: j-th group holds
+                // the pairs (0..j-1, j).
+                int64_t j = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)item)) * 0.5);
+                while (j * (j - 1) / 2 > item) --j;
+                while ((j + 1) * j / 2 <= item) ++j;
+                const int64_t i = item - j * (j - 1) / 2;
+                a = order[i];
+                b = order[j];
+            } else if (mode == kRect) {
+                a = item / nY;
+                b = item - a * nY;
             } else {
-                D[item] = ok ? d : (AT)__builtin_nan("");
+                a = pairs[2 * item];
+                b = pairs[2 * item + 1];
+            }
+            // a pair-list entry outside the collections yields NaN (swept as (0, 0))
+            const bool ok = a >= 0 && a < nX && b >= 0 && b < nY;
+            a = ok ? a : 0;
+            b = ok ? b : 0;
+            const int64_t xa = offX[a], la = offX[a + 1] - xa;
+            const int64_t yb = offY[b], lb = offY[b + 1] - yb;
+            const CT *ra = rowsX + (xa + a) * S;
+            const CT *rb = rowsY + (yb + b) * S;
+            // shorter operand across the lanes
+            const bool swap = lb > la;
+            const CT *rowsA = swap ? rb : ra;
+            const CT *rowsB = swap ? ra : rb;
+            const int nA = (int)(swap ? lb : la);
+            const int nB = (int)(swap ? la : lb);
+            const int k = (nB + kWave - 1) / kWave;
+            // Pairs wider than one wave are swept by the single-pair path instead.
+            if (k <= KMAX) {
+                // d is the same in every lane; every lane stores it (one
+                // transaction), so the loop body holds no lane-conditional branch.
+                const AT d = sweep_dispatch<CT, AT, DIMT, PM, 1>(k, rowsA, nA, rowsB, nB, ca);
+                if (mode == kSymmetric) {
+                    D[a * nX + b] = d;
+                    D[b * nX + a] = d;
+                } else {
+                    D[item] = ok ? d : (AT)__builtin_nan("");
+                }
             }
         }
     }
@@ -182,7 +190,8 @@ hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hip
     return by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
         hipLaunchKernelGGL((batch_kernel<CT, AT, DIMT, PM>), dim3(a.grid), dim3(kWave), 0, st,
                            (const CT *)a.rowsX, (const CT *)a.rowsY, a.offX, a.offY, a.order, a.pairs, a.nX,
-                           a.nY, a.nItems, a.mode, CostArgs<CT>::make(cp), (AT *)a.D, a.ticket);
+                           a.nY, a.nItems, a.mode, CostArgs<CT>::make(cp), (AT *)a.D, a.ticket,
+                           a.chunk > 1 ? a.chunk : 1);
         return hipGetLastError();
     });
 }

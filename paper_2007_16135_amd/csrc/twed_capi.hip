@@ -556,7 +556,13 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
         if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
     }
     if (b.nItems > 0) {
-        b.grid = (int)std::min<int64_t>(b.nItems, workers);
+        // items per ticket: about 64k cells of work per ticket for short
+        // pairs, while leaving at least four tickets per wave
+        const double cells = (double)totX / (double)nX * (double)totY / (double)nY;
+        int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(65536.0 / std::max(cells, 1.0))));
+        chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, b.nItems / (4 * (int64_t)workers)));
+        b.chunk = (int)chunk;
+        b.grid = (int)std::min<int64_t>((b.nItems + chunk - 1) / chunk, workers);
         e = launch_batch(prec, cp, b, st);
         if (e != hipSuccess) return fail_hip(e, "batch launch");
     }

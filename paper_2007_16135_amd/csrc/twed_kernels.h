@@ -161,6 +161,7 @@ struct BatchArgs {
     void *D;
     uint32_t *ticket;            // one word, zero
     int grid;
+    int chunk;                   // consecutive items per ticket (0 or 1: one)
 };
 hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hipStream_t st);
 int batch_kmax(int dimt);
