@@ -254,10 +254,12 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
             __hip_atomic_store(&sh.cons[w], need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
 
-        // One step: sweep row t - lane with `use`, prefetch row t + 1 - lane
-        // into `fill`.  Steps alternate the two row buffers, so the
-        // prefetched row never has to be copied.
-        auto step = [&](int i, Row<CT, DIMT> &use, Row<CT, DIMT> &fill) {
+        // One step: sweep row t - lane with `use`, prefetch row t + kAhead -
+        // lane into `fill`.  Steps rotate the row buffers, so the prefetched
+        // row never has to be copied.  SP (tile sweeps): this sub-chunk holds
+        // a step where top-row cells enter or boundary cells leave; the other
+        // sub-chunks run without testing for them at every step.
+        auto step = [&]<bool SP>(int i, Row<CT, DIMT> &use, Row<CT, DIMT> &fill) {
             const int t = t0 + i;
             load_row<CT, DIMT>(rowsA_lane, t + kAhead, fill);
 
@@ -278,6 +280,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
                         (void)lane_row_sibling<CT, AT, DIMT, PM, K, REC, false>(L, use, left, sh_xo, xl, ca.p,
                                                                                 ca.invp);
                 }
+              if constexpr (SP) {
                 // the lane sits on row 0: its top-row cells replace the pad state
                 if (io.top != nullptr && t < kWave) {
                     const bool own = t == lane;
@@ -323,6 +326,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
                     }
                     io.right[t - lstar] = Pair2<AT>{lane_value(dp, lstar), lane_value(x, lstar)};
                 }
+              }
             } else {
                 lane_row<CT, AT, DIMT, PM, K>(L, use, left, sh_xo, xl, ca.nu, ca.p, ca.invp, beta);
             }
@@ -362,30 +366,53 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
                 col_x = collect(xl, col_x);
             }
         };
-        int i = 0;
-        if constexpr (kAhead == 1) {
-            for (; i + 1 < steps; i += 2) {
-                step(i, cur, nxt);
-                step(i + 1, nxt, cur);
+        auto run = [&]<bool SP>() {
+            int i = 0;
+            if constexpr (kAhead == 1) {
+                for (; i + 1 < steps; i += 2) {
+                    step.template operator()<SP>(i, cur, nxt);
+                    step.template operator()<SP>(i + 1, nxt, cur);
+                }
+                if (i < steps) {
+                    step.template operator()<SP>(i, cur, nxt);
+                    cur = nxt;
+                }
+            } else {
+                // ring[k] holds row t + k (k < kAhead) at the start of each
+                // run of kAhead + 1 steps; sub-chunks are multiples of that
+                // run except at the end of the sweep, where the ring is
+                // shifted step by step
+                constexpr int R = kAhead + 1;
+                for (; i + R <= steps; i += R) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k)
+                        step.template operator()<SP>(i + k, ring[k], ring[(k + kAhead) % R]);
+                }
+                for (; i < steps; ++i) {
+                    step.template operator()<SP>(i, ring[0], ring[kAhead]);
+#pragma unroll
+                    for (int k = 0; k < kAhead; ++k) ring[k] = ring[k + 1];
+                }
             }
-            if (i < steps) {
-                step(i, cur, nxt);
-                cur = nxt;
+        };
+        if constexpr (TILE) {
+            // does a lane reach row 0 (top row), nA (bottom row) or a
+            // checkpoint row in this sub-chunk, or is this the strip that
+            // hands out column nB at every step?
+            const int r_lo = t0 - (kWave - 1), r_hi = t0 + steps - 1;  // rows the lanes touch
+            bool sp = (io.top != nullptr && t0 < kWave) || (io.right != nullptr && result_strip) ||
+                      (io.bottom != nullptr && nA >= r_lo && nA <= r_hi);
+            if (io.ckrow != nullptr) {
+                // the two multiples of ck_rows (>= 64) at or below r_hi cover
+                // the at most 95 rows of the range
+                const int m = r_hi / io.ck_rows * io.ck_rows;
+                for (int q = m; q >= m - io.ck_rows; q -= io.ck_rows)
+                    sp = sp || (q >= io.ck_rows && q >= r_lo && q < nA);
             }
+            if (sp) run.template operator()<true>();
+            else run.template operator()<false>();
         } else {
-            // ring[k] holds row t + k (k < kAhead) at the start of each run of
-            // kAhead + 1 steps; sub-chunks are multiples of that run except
-            // at the end of the sweep, where the ring is shifted step by step
-            constexpr int R = kAhead + 1;
-            for (; i + R <= steps; i += R) {
-#pragma unroll
-                for (int k = 0; k < R; ++k) step(i + k, ring[k], ring[(k + kAhead) % R]);
-            }
-            for (; i < steps; ++i) {
-                step(i, ring[0], ring[kAhead]);
-#pragma unroll
-                for (int k = 0; k < kAhead; ++k) ring[k] = ring[k + 1];
-            }
+            run.template operator()<false>();
         }
 
         const int tend = t0 + steps;        // steps done so far
