@@ -175,6 +175,94 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
     }
 }
 
+// One short query against many series: one lane per pair.  The query (at
+// most kLaneMaxQuery samples) sits in LDS and every lane reads the same row
+// at the same time (a broadcast); each lane sweeps its own series column by
+// column with the query's DP column in registers.  Every cell is evaluated
+// with the arithmetic of lane_row (transposed, which changes nothing: the
+// point and time terms are symmetric and the minimum is exact), so results
+// are bitwise those of the wave-per-pair sweep and of twed_pair.  It
+// replaces that sweep for this shape because a wave per pair would spend
+// most of its lanes and steps filling and draining a 64-lane pipeline for a
+// few hundred cells.
+template <typename CT, typename AT, int DIMT, int PM>
+__global__ __launch_bounds__(kWave) void batch_lane_kernel(const CT *__restrict__ rowsQ, int nQ,
+                                                           const CT *__restrict__ rowsY,
+                                                           const int64_t *__restrict__ offY, int64_t nY,
+                                                           CostArgs<CT> ca, AT *D, uint32_t *ticket)
+{
+    constexpr int S = Row<CT, DIMT>::kStride;
+    constexpr int QM = kLaneMaxQuery;
+    __shared__ CT q[(QM + 1) * S];
+    const int lane = threadIdx.x;
+    for (int k = lane; k < (nQ + 1) * S; k += kWave) q[k] = rowsQ[k];
+    __syncthreads();
+    const AT INF = pinf<AT>();
+    for (;;) {
+        const int64_t first = (int64_t)next_ticket(ticket) * kWave;
+        if (first >= nY) break;
+        const int64_t item = first + lane;
+        const bool ok = item < nY;
+        const int64_t b = ok ? item : first;  // idle lanes repeat a pair and store nothing
+        const int64_t yb = offY[b];
+        const int lb = (int)(offY[b + 1] - yb);
+        const CT *rb = rowsY + (yb + b) * S;
+        int maxL = lb;
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m >>= 1) {
+            const int o = __shfl_xor(maxL, m, kWave);
+            maxL = o > maxL ? o : maxL;
+        }
+        // DP(i, j-1) and X(i, j-1) of the query rows i = 0..nQ
+        AT up[QM + 1], xq[QM + 1];
+        up[0] = AT(0);
+        xq[0] = AT(0);
+#pragma unroll
+        for (int i = 1; i <= QM; ++i) {
+            up[i] = INF;
+            xq[i] = INF;
+        }
+        AT res = INF;
+        for (int j = 1; j <= maxL; ++j) {
+            Row<CT, DIMT> bj;
+            load_row<CT, DIMT>(rb, j <= lb ? j : lb, bj);
+            const AT bdel = (AT)bj.del;
+            AT above = INF;       // DP(i-1, j), starting at the pad row
+            AT diag = xq[0];      // X(i-1, j-1)
+            // an offset the compiler cannot see through: the query rows are
+            // read from LDS in every column instead of being hoisted out of
+            // the column loop (all of them would not fit in registers)
+            uint32_t qo = 0;
+            asm volatile("" : "+v"(qo));
+#pragma unroll
+            for (int i = 1; i <= QM; ++i) {
+                if (i <= nQ) {
+                    Row<CT, DIMT> a;
+#pragma unroll
+                    for (int k = 0; k < DIMT; ++k) a.x[k] = q[qo + i * S + k];
+                    a.t = q[qo + i * S + DIMT];
+                    a.del = q[qo + i * S + DIMT + 1];
+                    const CT dist = point_dist<DIMT, PM, CT>(a.x, bj.x, ca.p, ca.invp);
+                    const AT e = (AT)fma_(ca.nu, fabs_(a.t - bj.t), dist);
+                    const AT v = dmin(dmin(diag + e, above + (AT)a.del), up[i] + bdel);
+                    diag = xq[i];
+                    xq[i] = v + e;
+                    up[i] = v;
+                    above = v;
+                }
+            }
+            up[0] = INF;
+            xq[0] = INF;
+            AT last = up[1];
+#pragma unroll
+            for (int i = 2; i <= QM; ++i)
+                if (i == nQ) last = up[i];
+            res = j == lb ? last : res;
+        }
+        if (ok) D[item] = res;
+    }
+}
+
 template <typename CT, typename AT, int DIMT, int PM>
 static int batch_occupancy()
 {
@@ -192,6 +280,18 @@ hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hip
                            (const CT *)a.rowsX, (const CT *)a.rowsY, a.offX, a.offY, a.order, a.pairs, a.nX,
                            a.nY, a.nItems, a.mode, CostArgs<CT>::make(cp), (AT *)a.D, a.ticket,
                            a.chunk > 1 ? a.chunk : 1);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_lane(Prec prec, const CostParams &cp, const void *rowsQ, int nQ, const void *rowsY,
+                            const int64_t *offY, int64_t nY, void *D, uint32_t *ticket, int grid, hipStream_t st)
+{
+    if (nQ < 1 || nQ > kLaneMaxQuery) return hipErrorInvalidValue;
+    return by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
+        hipLaunchKernelGGL((batch_lane_kernel<CT, AT, DIMT, PM>), dim3(grid), dim3(kWave), 0, st,
+                           (const CT *)rowsQ, nQ, (const CT *)rowsY, offY, nY, CostArgs<CT>::make(cp), (AT *)D,
+                           ticket);
         return hipGetLastError();
     });
 }

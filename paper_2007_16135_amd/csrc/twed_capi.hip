@@ -555,7 +555,12 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
         e = launch_batch_diag_zero(prec, Dk, nX, st);
         if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
     }
-    if (b.nItems > 0) {
+    if (b.nItems > 0 && !pairs && !sym && nX == 1 && maxX <= kLaneMaxQuery) {
+        // one short query: a lane per pair
+        e = launch_batch_lane(prec, cp, L.rowsX, (int)maxX, L.rowsY, (const int64_t *)L.offY, nY, Dk,
+                              (uint32_t *)L.zero, (int)std::min<int64_t>((nY + 63) / 64, workers), st);
+        if (e != hipSuccess) return fail_hip(e, "batch launch");
+    } else if (b.nItems > 0) {
         // items per ticket: about 64k cells of work per ticket for short
         // pairs, while leaving at least four tickets per wave
         const double cells = (double)totX / (double)nX * (double)totY / (double)nY;

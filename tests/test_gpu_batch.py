@@ -165,3 +165,34 @@ def test_paper_shaped_rn_query_vs_oracle():
     ref = oracle.get().pairs(q.X, q.T, q.off, col.X, col.T, col.off, pairs, 1e-3, 1.0, 2.0, threads=8)
     assert max_rel(D, ref) <= 1e-12
     assert D[0] == 0.0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_acc64"])
+def test_short_query_lane_mode_bitwise(prec):
+    """One query of at most 32 samples against a collection runs one lane per
+    pair; every entry must be bitwise what twed_pair gives for that pair
+    (ragged collection lengths, some shorter and some much longer than the
+    query, a count that is not a multiple of 64), and within the precision's
+    bar of the oracle."""
+    rng = np.random.default_rng(17)
+    for nq, dim, p in ((1, 1, 1.0), (5, 3, 2.0), (32, 8, 2.0), (28, 28, 2.0), (17, 2, 3.0)):
+        col = synth.batch_collection(131, 1, 90, seed=100 + nq)
+        Y = rng.standard_normal((len(col.T), dim)).cumsum(0)
+        q = rng.standard_normal((nq, dim)).cumsum(0)
+        tq = np.cumsum(rng.exponential(1.0, nq))
+        dt = torch.float64 if prec == "f64" else torch.float32
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+        say(f"lane mode {prec} query {nq} dim {dim}")
+        D = tw.twed_batch(f(q), f(tq), np.array([0, nq]), f(Y), f(col.T), col.off, nu=0.05, lam=0.7, p=p,
+                          precision=prec)
+        torch.cuda.synchronize()
+        D = D.cpu().numpy().reshape(-1)
+        for j in range(col.count):
+            yj = Y[col.off[j]:col.off[j + 1]]
+            tj = col.T[col.off[j]:col.off[j + 1]]
+            v = float(tw.twed_pair(f(q), f(tq), f(yj), f(tj), 0.05, 0.7, p, prec).item())
+            assert D[j] == v, (j, D[j], v)
+        rounded = (lambda a: a) if prec == "f64" else (lambda a: np.asarray(a, np.float32).astype(np.float64))
+        ref = oracle.get().pairs(rounded(q), rounded(tq), np.array([0, nq]), rounded(Y), rounded(col.T), col.off,
+                                 np.array([(0, j) for j in range(col.count)]), 0.05, 0.7, p)
+        assert max_rel(D, ref) <= {"f64": 1e-12, "f32": 1e-5, "f32_acc64": 1e-6}[prec]
