@@ -106,3 +106,29 @@ def test_dp_paths():
         want = orc.dtw(A, B, 2.0)
         assert abs(float(v.item()) - want) <= 1e-12 * want
         assert abs(cost - want) <= 1e-10 * want
+
+
+def test_dp_paths_long_and_wide_strips():
+    """A DTW path whose forward sweep uses strips of eight columns (a wide
+    pair) and blocks of 256; an edit path of 3000 x 2500 tokens."""
+    rng = np.random.default_rng(12)
+    orc = oracle.get()
+    nA, nB = 3000, 2500
+    A = rng.standard_normal((nA, 1)).cumsum(0)
+    B = rng.standard_normal((nB, 1)).cumsum(0)
+    say("dtw path 3000x2500 strip_k 8")
+    v, path = tw.twed_dp_path("dtw", dev(A, "f64"), dev(B, "f64"), p=1.0, block=256, strip_k=8)
+    P = path.cpu().numpy()
+    _check_path(P, nA, nB, False)
+    want = orc.dtw(A, B, 1.0)
+    assert abs(float(v.item()) - want) <= 1e-12 * want
+    cost = sum(abs(A[i - 1, 0] - B[j - 1, 0]) for i, j in P[1:])
+    assert abs(cost - want) <= 1e-10 * want
+    a, b = tokens(rng, nA, 6), tokens(rng, nB, 6)
+    say("edit path 3000x2500")
+    v, path = tw.twed_dp_path("edit", dev(a, "f32_acc64"), dev(b, "f32_acc64"), precision="f32_acc64", block=512)
+    P = path.cpu().numpy()
+    _check_path(P, nA, nB, True)
+    cost = sum(1 if (i1 - i0) + (j1 - j0) == 1 else int(a[i1 - 1] != b[j1 - 1])
+               for (i0, j0), (i1, j1) in zip(P[:-1], P[1:]))
+    assert cost == float(v.item()) == orc.edit(a, b)

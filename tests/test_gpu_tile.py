@@ -177,3 +177,22 @@ def test_path_single_samples():
     """nA = 1 or nB = 1: the only admissible paths are a match then deletions."""
     for nA, nB in ((1, 1), (1, 9), (9, 1)):
         _path_case(61, nA, nB, 1, "f64", 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_acc64"])
+def test_high_dimensional_tiles_and_paths(prec):
+    """Samples of 16 and 28 components: a tile from oracle boundaries and a
+    multi-block path."""
+    for dim in (16, 28):
+        c = synth.random_pair(80 + dim, 81 + dim, 400, 330, dim, irregular=True, nu=0.02, lam=0.9, p=2.0)
+        A, TA, B, TB = host_inputs(c, prec)
+        DP, X = oracle.get().matrix_x(A, TA, B, TB, c.nu, c.lam, c.p)
+        dA, dTA, dB, dTB = operands(c, prec)
+        r0, r1, c0, c1 = 100, 400, 70, 300
+        say(f"tile dim {dim} {prec}")
+        corner, bot, rig = tw.twed_pair_tile(dA, dTA, dB, dTB, r0, r1, c0, c1, cells(DP, X, r0, slice(c0, c1 + 1)),
+                                             cells(DP, X, slice(r0, r1 + 1), c0), c.nu, c.lam, c.p, prec)
+        torch.cuda.synchronize()
+        close(bot.cpu().numpy()[:, 0], DP[r1, c0:c1 + 1], RTOL[prec])
+        close(rig.cpu().numpy()[:, 1], X[r0:r1 + 1, c1], RTOL[prec])
+        _path_case(90 + dim, 260, 300, dim, prec, 64)
