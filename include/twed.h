@@ -275,6 +275,33 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
                        const twed_params *prm, void *D,
                        void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* A batch of fixed shape prepared once and run many times (the paper's batch
+ * mode, as twed_batch).  twed_batch_plan_create checks the offsets and
+ * parameters, lays out `workspace` (twed_batch_workspace_size bytes; the
+ * caller keeps it allocated and untouched while the plan lives) and copies
+ * the offsets and the longest-first order of the series into it with a
+ * synchronous copy.  offY == NULL plans the symmetric matrix of X (nY is
+ * then ignored);
+ * nPairs > 0 plans a pair list of that length, nPairs == 0 the full matrix.
+ * twed_batch_plan_run then enqueues kernels only on `stream` (staging, which
+ * also clears the work ticket, the sweeps, the mirror and the widening), so
+ * a caller can capture it in a HIP graph and replay it; X, TX, Y, TY, pairs
+ * and D as for twed_batch, with the planned shapes (Y, TY NULL exactly for a
+ * symmetric plan, pairs given exactly for a pair-list plan).  Runs on one
+ * plan must not overlap: they share the workspace.  The plan is a host
+ * object; twed_batch_plan_destroy frees it (not the workspace). */
+typedef struct twed_batch_plan twed_batch_plan;
+
+twed_status twed_batch_plan_create(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY,
+                                   int64_t nPairs, const twed_params *prm,
+                                   void *workspace, size_t ws_bytes, twed_batch_plan **plan);
+
+twed_status twed_batch_plan_run(const twed_batch_plan *plan, const void *X, const void *TX,
+                                const void *Y, const void *TY, const int64_t *pairs, void *D,
+                                hipStream_t stream);
+
+void twed_batch_plan_destroy(twed_batch_plan *plan);
+
 /* Longest shorter-operand length a pair may have to be swept by a single
  * wave inside the batched kernel (longer pairs use the single-pair sweep). */
 int64_t twed_batch_max_short_length(int32_t dim);

@@ -22,6 +22,7 @@ ALGOS = {"auto": 0, "wavefront": 1, "diagonal": 2}
 EXPORTS = [
     "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_matrix",
     "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
+    "twed_batch_plan_create", "twed_batch_plan_run", "twed_batch_plan_destroy",
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
     "twed_pair_tune", "twed_tune_clear",
     "twed_pair_tile_workspace_size", "twed_pair_tile", "twed_pair_path_workspace_size", "twed_pair_path",
@@ -75,6 +76,13 @@ def load_library(path: str = LIB_PATH):
     L.twed_batch.argtypes = [_vp, _vp, _i64p, _i64, _vp, _vp, _i64p, _i64, _vp, _i64, _pp, _vp, _vp,
                              ctypes.c_size_t, _vp]
     L.twed_batch.restype = ctypes.c_int
+    L.twed_batch_plan_create.argtypes = [_i64p, _i64, _i64p, _i64, _i64, _pp, _vp, ctypes.c_size_t,
+                                         ctypes.POINTER(_vp)]
+    L.twed_batch_plan_create.restype = ctypes.c_int
+    L.twed_batch_plan_run.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.twed_batch_plan_run.restype = ctypes.c_int
+    L.twed_batch_plan_destroy.argtypes = [_vp]
+    L.twed_batch_plan_destroy.restype = None
     L.twed_pair_tune.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, ctypes.c_size_t, _vp,
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.twed_pair_tune.restype = ctypes.c_int
@@ -452,6 +460,76 @@ def twed_batch(X, TX, offX, Y=None, TY=None, offY=None, pairs=None, nu=1e-3, lam
     _check(L.twed_batch(X2.data_ptr(), TX.data_ptr(), px, nX, Yp, TYp, py, nY, pp, nP,
                         ctypes.byref(prm), D.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
     return D
+
+
+class BatchPlan:
+    """A batch of fixed shape planned once (offsets checked and uploaded, the
+    workspace laid out) and run many times; run() only enqueues kernels, so
+    it can be captured in a torch CUDA graph and replayed.  The plan keeps
+    its workspace tensor alive; runs on one plan must not overlap."""
+
+    def __init__(self, offX, offY=None, n_pairs=0, dim=1, nu=1e-3, lam=1.0, p=1.0, precision="f32",
+                 device="cuda"):
+        torch = _torch()
+        offX, px = _offsets(offX)
+        self.nX = len(offX) - 1
+        self.sym = offY is None
+        if self.sym:
+            py, self.nY = None, self.nX
+        else:
+            offYa, py = _offsets(offY)
+            self.nY = len(offYa) - 1
+        self.n_pairs = int(n_pairs)
+        self.precision = precision
+        self.dim = dim
+        self.prm = make_params(nu, lam, p, dim, precision)
+        L = load_library()
+        need = L.twed_batch_workspace_size(px, self.nX, py, 0 if self.sym else self.nY, ctypes.byref(self.prm))
+        self.ws = _workspace(need, torch.device(device))
+        h = _vp()
+        self._h = None
+        _check(L.twed_batch_plan_create(px, self.nX, py, 0 if self.sym else self.nY, self.n_pairs,
+                                        ctypes.byref(self.prm), self.ws.data_ptr(), self.ws.numel(),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def output(self):
+        torch = _torch()
+        shape = (self.n_pairs,) if self.n_pairs > 0 else (self.nX, self.nY)
+        return torch.empty(shape, dtype=output_dtype(self.precision), device=self.ws.device)
+
+    def run(self, X, TX, Y=None, TY=None, pairs=None, D=None, stream=None):
+        torch = _torch()
+        dt = input_dtype(self.precision)
+        X2 = X if X.dim() == 2 else X.reshape(-1, 1)
+        _dev(X2, dt, "X"); _dev(TX, dt, "TX")
+        if X2.shape[1] != self.dim:
+            raise ValueError("X has a different dimension than the plan")
+        Yp = TYp = None
+        if Y is not None:
+            Y2 = Y if Y.dim() == 2 else Y.reshape(-1, 1)
+            _dev(Y2, dt, "Y"); _dev(TY, dt, "TY")
+            Yp, TYp = Y2.data_ptr(), TY.data_ptr()
+        pp = None
+        if pairs is not None:
+            _dev(pairs, torch.int64, "pairs")
+            pp = pairs.data_ptr()
+        if D is None:
+            D = self.output()
+        _check(load_library().twed_batch_plan_run(self._h, X2.data_ptr(), TX.data_ptr(), Yp, TYp, pp,
+                                                  D.data_ptr(), _stream(stream)))
+        return D
+
+    def close(self):
+        if self._h is not None:
+            load_library().twed_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def twed_stream_check(stream=None):

@@ -16,6 +16,7 @@
 #include <tuple>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -322,6 +323,204 @@ BatchLayout batch_layout(char *base, int64_t totX, int64_t nX, int64_t maxX, int
     return L;
 }
 
+// ---- batch: preparation (host), upload and enqueue --------------------------------
+//
+// twed_batch = prepare + upload + enqueue in one call.  A twed_batch_plan
+// keeps the prepared state so that later runs enqueue kernels only (and can
+// therefore be captured in a HIP graph).
+struct BatchPlan {
+    twed_params prm;
+    Prec prec;
+    CostParams cp;
+    BatchLayout L;
+    std::vector<int64_t> offX, offY;  // host copies (offY empty when symmetric)
+    std::vector<int32_t> order;       // longest-first order (symmetric)
+    int64_t nX, nY, maxX, maxY, totX, totY, nPairs;
+    bool sym, list;
+};
+
+twed_status batch_prepare(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY, bool sym, bool list,
+                          int64_t nPairs, const twed_params *prm, void *workspace, size_t ws_bytes, BatchPlan &P)
+{
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    int64_t maxX, totX, maxY, totY;
+    s = check_offsets(offX, nX, &maxX, &totX);
+    if (s != TWED_OK) return s;
+    if (sym) {
+        if (offY) return fail(TWED_ERR_INVALID, "Y == NULL requires TY == NULL and offY == NULL");
+        if (nY != nX) return fail(TWED_ERR_INVALID, "Y == NULL requires nY == nX");
+        maxY = maxX;
+        totY = totX;
+    } else {
+        s = check_offsets(offY, nY, &maxY, &totY);
+        if (s != TWED_OK) return s;
+    }
+    if (list && nPairs < 0) return fail(TWED_ERR_INVALID, "nPairs must be >= 0");
+    if (nX * nY > (int64_t(1) << 40)) return fail(TWED_ERR_UNSUPPORTED, "too many pairs");
+    const int64_t kshort = twed_batch_max_short_length(prm->dim);
+    if (list && std::min(maxX, maxY) > kshort)
+        return fail(TWED_ERR_UNSUPPORTED, "pair lists need one collection of series no longer than "
+                                          "twed_batch_max_short_length(dim)");
+    const Prec prec = resolve(prm, std::max(maxX, maxY));
+    const BatchLayout need = batch_layout(nullptr, totX, nX, maxX, totY, nY, maxY, sym, nX * nY, prm, prec);
+    s = check_workspace(workspace, ws_bytes, need.total);
+    if (s != TWED_OK) return s;
+    P.prm = *prm;
+    P.prec = prec;
+    P.cp = cost_params(prm);
+    P.L = batch_layout((char *)workspace, totX, nX, maxX, totY, nY, maxY, sym, nX * nY, prm, prec);
+    P.offX.assign(offX, offX + nX + 1);
+    if (!sym) P.offY.assign(offY, offY + nY + 1);
+    P.order.clear();
+    if (sym) {
+        P.order.resize((size_t)nX);
+        std::iota(P.order.begin(), P.order.end(), 0);
+        std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t a, int32_t b) {
+            return offX[a + 1] - offX[a] > offX[b + 1] - offX[b];
+        });
+    }
+    P.nX = nX;
+    P.nY = nY;
+    P.maxX = maxX;
+    P.maxY = maxY;
+    P.totX = totX;
+    P.totY = totY;
+    P.nPairs = list ? nPairs : 0;
+    P.sym = sym;
+    P.list = list;
+    return TWED_OK;
+}
+
+// Copies the offsets and the order to the workspace (asynchronous unless
+// `sync`, in which case the copies have completed on return).
+twed_status batch_upload(const BatchPlan &P, hipStream_t st, bool sync)
+{
+    const BatchLayout &L = P.L;
+    hipError_t e;
+    if (sync) {
+        e = hipMemcpy(L.offX, P.offX.data(), (size_t)(P.nX + 1) * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !P.sym) e = hipMemcpy(L.offY, P.offY.data(), (size_t)(P.nY + 1) * 8,
+                                                    hipMemcpyHostToDevice);
+        if (e == hipSuccess && P.sym) e = hipMemcpy(L.order, P.order.data(), (size_t)P.nX * 4, hipMemcpyHostToDevice);
+    } else {
+        e = hipMemcpyAsync(L.offX, P.offX.data(), (size_t)(P.nX + 1) * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !P.sym) e = hipMemcpyAsync(L.offY, P.offY.data(), (size_t)(P.nY + 1) * 8,
+                                                         hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && P.sym) e = hipMemcpyAsync(L.order, P.order.data(), (size_t)P.nX * 4,
+                                                        hipMemcpyHostToDevice, st);
+    }
+    if (e != hipSuccess) return fail_hip(e, "offset upload");
+    return TWED_OK;
+}
+
+// Kernels only: staging (which also clears the work ticket), the sweeps, the
+// mirror of the symmetric case and the widening of TWED_AUTO results.
+twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, const void *Y, const void *TY,
+                          const int64_t *pairs, void *D, hipStream_t st)
+{
+    const BatchLayout &L = P.L;
+    const twed_params *prm = &P.prm;
+    const Prec prec = P.prec;
+    const CostParams &cp = P.cp;
+    const int64_t nX = P.nX, nY = P.nY, maxX = P.maxX, maxY = P.maxY, totX = P.totX, totY = P.totY;
+    const int64_t nPairs = P.nPairs;
+    const bool sym = P.sym;
+    const int64_t *offX = P.offX.data();
+    const int64_t *offY = sym ? nullptr : P.offY.data();
+    const int64_t kshort = twed_batch_max_short_length(prm->dim);
+    if (P.list && nPairs == 0) return TWED_OK;
+    twed_status s = TWED_OK;
+    hipError_t e;
+    e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, totX + nX, L.rowsX,
+                     (uint32_t *)L.zero, 1, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    if (!sym) {
+        e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, totY + nY, L.rowsY, nullptr, 0,
+                         st);
+        if (e != hipSuccess) return fail_hip(e, "staging launch");
+    }
+    const bool widen = needs_widen(prm, prec);
+    void *Dk = widen ? L.tmpD : D;
+    const int64_t nOut = pairs ? nPairs : nX * nY;
+
+    BatchArgs b{};
+    b.rowsX = L.rowsX;
+    b.rowsY = L.rowsY;
+    b.offX = (const int64_t *)L.offX;
+    b.offY = (const int64_t *)L.offY;
+    b.order = (const int32_t *)L.order;
+    b.pairs = pairs;
+    b.nX = nX;
+    b.nY = nY;
+    b.mode = pairs ? kPairList : (sym ? kSymmetric : kRect);
+    b.nItems = pairs ? nPairs : (sym ? nX * (nX - 1) / 2 : nX * nY);
+    b.D = Dk;
+    b.ticket = (uint32_t *)L.zero;
+    if (b.nItems > 0xffffffffLL) return fail(TWED_ERR_UNSUPPORTED, "more than 2^32 - 1 pairs in one call");
+    const int workers = batch_max_workers(prec, cp);
+    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+    if (sym) {
+        e = launch_batch_diag_zero(prec, Dk, nX, st);
+        if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
+    }
+    if (b.nItems > 0 && !pairs && !sym && nX == 1 && maxX <= kLaneMaxQuery) {
+        // one short query: a lane per pair
+        e = launch_batch_lane(prec, cp, L.rowsX, (int)maxX, L.rowsY, (const int64_t *)L.offY, nY, Dk,
+                              (uint32_t *)L.zero, (int)std::min<int64_t>((nY + 63) / 64, workers), st);
+        if (e != hipSuccess) return fail_hip(e, "batch launch");
+    } else if (b.nItems > 0) {
+        // items per ticket: about 64k cells of work per ticket for short
+        // pairs, while leaving at least four tickets per wave
+        const double cells = (double)totX / (double)nX * (double)totY / (double)nY;
+        int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(65536.0 / std::max(cells, 1.0))));
+        chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, b.nItems / (4 * (int64_t)workers)));
+        b.chunk = (int)chunk;
+        b.grid = (int)std::min<int64_t>((b.nItems + chunk - 1) / chunk, workers);
+        e = launch_batch(prec, cp, b, st);
+        if (e != hipSuccess) return fail_hip(e, "batch launch");
+    }
+
+    // pairs whose shorter series exceeds one wave: single-pair sweeps
+    if (!pairs && std::min(maxX, maxY) > kshort) {
+        const size_t S = (size_t)row_stride(prec, cp.dimt), cs = cost_size(prec), as = acc_size(prec);
+        const int64_t maxlen = std::max(maxX, maxY);
+        const int64_t nflags = (maxlen + 63) / 64, zero_words = nflags + kTailWords;
+        const int64_t *offYh = sym ? offX : offY;
+        for (int64_t i = 0; i < nX; ++i) {
+            const int64_t li = offX[i + 1] - offX[i];
+            if (li <= kshort) continue;
+            for (int64_t j = sym ? i + 1 : 0; j < nY; ++j) {
+                const int64_t lj = offYh[j + 1] - offYh[j];
+                if (lj <= kshort) continue;
+                const char *ra = (const char *)L.rowsX + (size_t)(offX[i] + i) * S * cs;
+                const char *rb = (const char *)L.rowsY + (size_t)(offYh[j] + j) * S * cs;
+                // the longer series streams, the shorter spreads over the lanes
+                const bool swap = lj > li;
+                const int64_t nA = swap ? lj : li, nB = swap ? li : lj;
+                // zero flags and ticket (the staging kernel's zeroing pass)
+                e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, 0, 0, 0, totX + nX, L.rowsX,
+                                 (uint32_t *)L.flags, zero_words, st);
+                if (e != hipSuccess) return fail_hip(e, "flag reset launch");
+                uint32_t *flags = (uint32_t *)L.flags;
+                char *dst = (char *)Dk + (size_t)(i * nY + j) * as;
+                s = run_pair_sweep(prec, cp, prm, swap ? rb : ra, swap ? ra : rb, nA, nB, L.bnd, flags,
+                                   flags + nflags, nullptr, dst, nullptr, st);
+                if (s != TWED_OK) return s;
+                if (sym) {
+                    e = launch_copy_one(prec, dst, (char *)Dk + (size_t)(j * nY + i) * as, st);
+                    if (e != hipSuccess) return fail_hip(e, "mirror launch");
+                }
+            }
+        }
+    }
+    if (widen) {
+        e = launch_widen((const float *)Dk, (double *)D, nOut, st);
+        if (e != hipSuccess) return fail_hip(e, "widen launch");
+    }
+    return TWED_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -471,146 +670,63 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
                        const twed_params *prm, void *D, void *workspace, size_t ws_bytes, hipStream_t st)
 {
     last_error().clear();
-    twed_status s = check_params(prm);
-    if (s != TWED_OK) return s;
+    if (!prm) return fail(TWED_ERR_INVALID, "params is NULL");
     if (!X || !TX || !D) return fail(TWED_ERR_INVALID, "NULL array argument");
-    int64_t maxX, totX, maxY, totY;
-    s = check_offsets(offX, nX, &maxX, &totX);
-    if (s != TWED_OK) return s;
     const bool sym = Y == nullptr;
-    if (sym) {
-        if (TY || offY) return fail(TWED_ERR_INVALID, "Y == NULL requires TY == NULL and offY == NULL");
-        if (nY != nX) return fail(TWED_ERR_INVALID, "Y == NULL requires nY == nX");
-        maxY = maxX;
-        totY = totX;
-    } else {
-        if (!TY) return fail(TWED_ERR_INVALID, "NULL array argument");
-        s = check_offsets(offY, nY, &maxY, &totY);
-        if (s != TWED_OK) return s;
-    }
-    if (pairs && nPairs < 0) return fail(TWED_ERR_INVALID, "nPairs must be >= 0");
-    if (nX * nY > (int64_t(1) << 40)) return fail(TWED_ERR_UNSUPPORTED, "too many pairs");
-    const int64_t kshort = twed_batch_max_short_length(prm->dim);
-    if (pairs && std::min(maxX, maxY) > kshort)
-        return fail(TWED_ERR_UNSUPPORTED, "pair lists need one collection of series no longer than "
-                                          "twed_batch_max_short_length(dim)");
-    const Prec prec = resolve(prm, std::max(maxX, maxY));
-    const BatchLayout need = batch_layout(nullptr, totX, nX, maxX, totY, nY, maxY, sym, nX * nY, prm, prec);
-    s = check_workspace(workspace, ws_bytes, need.total);
+    if (sym && TY) return fail(TWED_ERR_INVALID, "Y == NULL requires TY == NULL and offY == NULL");
+    if (!sym && !TY) return fail(TWED_ERR_INVALID, "NULL array argument");
+    BatchPlan P;
+    twed_status s = batch_prepare(offX, nX, offY, nY, sym, pairs != nullptr, nPairs, prm, workspace, ws_bytes, P);
     if (s != TWED_OK) return s;
-    const BatchLayout L = batch_layout((char *)workspace, totX, nX, maxX, totY, nY, maxY, sym, nX * nY, prm, prec);
-    const CostParams cp = cost_params(prm);
-    if (pairs && nPairs == 0) return TWED_OK;
+    if (P.list && nPairs == 0) return TWED_OK;
+    s = batch_upload(P, st, false);
+    if (s != TWED_OK) return s;
+    return batch_enqueue(P, X, TX, Y, TY, pairs, D, st);
+}
 
-    // longest-first order of the series (symmetric mode)
-    std::vector<int32_t> order;
-    if (sym) {
-        order.resize((size_t)nX);
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            return offX[a + 1] - offX[a] > offX[b + 1] - offX[b];
-        });
-    }
+}  // extern "C"
 
-    hipError_t e;
-    e = hipMemcpyAsync(L.offX, offX, (size_t)(nX + 1) * 8, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return fail_hip(e, "offset upload");
-    if (!sym) {
-        e = hipMemcpyAsync(L.offY, offY, (size_t)(nY + 1) * 8, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return fail_hip(e, "offset upload");
-    }
-    if (sym) {
-        e = hipMemcpyAsync(L.order, order.data(), (size_t)nX * 4, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return fail_hip(e, "order upload");
-    }
-    e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, totX + nX, L.rowsX,
-                     (uint32_t *)L.zero, 1, st);
-    if (e != hipSuccess) return fail_hip(e, "staging launch");
-    if (!sym) {
-        e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, totY + nY, L.rowsY, nullptr, 0,
-                         st);
-        if (e != hipSuccess) return fail_hip(e, "staging launch");
-    }
-    const bool widen = needs_widen(prm, prec);
-    void *Dk = widen ? L.tmpD : D;
-    const int64_t nOut = pairs ? nPairs : nX * nY;
+struct twed_batch_plan {
+    BatchPlan p;
+};
 
-    BatchArgs b{};
-    b.rowsX = L.rowsX;
-    b.rowsY = L.rowsY;
-    b.offX = (const int64_t *)L.offX;
-    b.offY = (const int64_t *)L.offY;
-    b.order = (const int32_t *)L.order;
-    b.pairs = pairs;
-    b.nX = nX;
-    b.nY = nY;
-    b.mode = pairs ? kPairList : (sym ? kSymmetric : kRect);
-    b.nItems = pairs ? nPairs : (sym ? nX * (nX - 1) / 2 : nX * nY);
-    b.D = Dk;
-    b.ticket = (uint32_t *)L.zero;
-    if (b.nItems > 0xffffffffLL) return fail(TWED_ERR_UNSUPPORTED, "more than 2^32 - 1 pairs in one call");
-    const int workers = batch_max_workers(prec, cp);
-    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
-    if (sym) {
-        e = launch_batch_diag_zero(prec, Dk, nX, st);
-        if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
-    }
-    if (b.nItems > 0 && !pairs && !sym && nX == 1 && maxX <= kLaneMaxQuery) {
-        // one short query: a lane per pair
-        e = launch_batch_lane(prec, cp, L.rowsX, (int)maxX, L.rowsY, (const int64_t *)L.offY, nY, Dk,
-                              (uint32_t *)L.zero, (int)std::min<int64_t>((nY + 63) / 64, workers), st);
-        if (e != hipSuccess) return fail_hip(e, "batch launch");
-    } else if (b.nItems > 0) {
-        // items per ticket: about 64k cells of work per ticket for short
-        // pairs, while leaving at least four tickets per wave
-        const double cells = (double)totX / (double)nX * (double)totY / (double)nY;
-        int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(65536.0 / std::max(cells, 1.0))));
-        chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, b.nItems / (4 * (int64_t)workers)));
-        b.chunk = (int)chunk;
-        b.grid = (int)std::min<int64_t>((b.nItems + chunk - 1) / chunk, workers);
-        e = launch_batch(prec, cp, b, st);
-        if (e != hipSuccess) return fail_hip(e, "batch launch");
-    }
+extern "C" {
 
-    // pairs whose shorter series exceeds one wave: single-pair sweeps
-    if (!pairs && std::min(maxX, maxY) > kshort) {
-        const size_t S = (size_t)row_stride(prec, cp.dimt), cs = cost_size(prec), as = acc_size(prec);
-        const int64_t maxlen = std::max(maxX, maxY);
-        const int64_t nflags = (maxlen + 63) / 64, zero_words = nflags + kTailWords;
-        const int64_t *offYh = sym ? offX : offY;
-        for (int64_t i = 0; i < nX; ++i) {
-            const int64_t li = offX[i + 1] - offX[i];
-            if (li <= kshort) continue;
-            for (int64_t j = sym ? i + 1 : 0; j < nY; ++j) {
-                const int64_t lj = offYh[j + 1] - offYh[j];
-                if (lj <= kshort) continue;
-                const char *ra = (const char *)L.rowsX + (size_t)(offX[i] + i) * S * cs;
-                const char *rb = (const char *)L.rowsY + (size_t)(offYh[j] + j) * S * cs;
-                // the longer series streams, the shorter spreads over the lanes
-                const bool swap = lj > li;
-                const int64_t nA = swap ? lj : li, nB = swap ? li : lj;
-                // zero flags and ticket (the staging kernel's zeroing pass)
-                e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, 0, 0, 0, totX + nX, L.rowsX,
-                                 (uint32_t *)L.flags, zero_words, st);
-                if (e != hipSuccess) return fail_hip(e, "flag reset launch");
-                uint32_t *flags = (uint32_t *)L.flags;
-                char *dst = (char *)Dk + (size_t)(i * nY + j) * as;
-                s = run_pair_sweep(prec, cp, prm, swap ? rb : ra, swap ? ra : rb, nA, nB, L.bnd, flags,
-                                   flags + nflags, nullptr, dst, nullptr, st);
-                if (s != TWED_OK) return s;
-                if (sym) {
-                    e = launch_copy_one(prec, dst, (char *)Dk + (size_t)(j * nY + i) * as, st);
-                    if (e != hipSuccess) return fail_hip(e, "mirror launch");
-                }
-            }
-        }
+twed_status twed_batch_plan_create(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY, int64_t nPairs,
+                                   const twed_params *prm, void *workspace, size_t ws_bytes, twed_batch_plan **out)
+{
+    last_error().clear();
+    if (!out) return fail(TWED_ERR_INVALID, "out is NULL");
+    if (!prm) return fail(TWED_ERR_INVALID, "params is NULL");
+    if (nPairs < 0) return fail(TWED_ERR_INVALID, "nPairs must be >= 0");
+    twed_batch_plan *plan = new (std::nothrow) twed_batch_plan();
+    if (!plan) return fail(TWED_ERR_DEVICE, "host allocation failed");
+    if (!offY) nY = nX;  // symmetric plan: nY is ignored, as in twed_batch_workspace_size
+    twed_status s = batch_prepare(offX, nX, offY, nY, offY == nullptr, nPairs > 0, nPairs, prm, workspace, ws_bytes,
+                                  plan->p);
+    if (s == TWED_OK) s = batch_upload(plan->p, nullptr, true);
+    if (s != TWED_OK) {
+        delete plan;
+        return s;
     }
-    if (widen) {
-        e = launch_widen((const float *)Dk, (double *)D, nOut, st);
-        if (e != hipSuccess) return fail_hip(e, "widen launch");
-    }
+    *out = plan;
     return TWED_OK;
 }
+
+twed_status twed_batch_plan_run(const twed_batch_plan *plan, const void *X, const void *TX, const void *Y,
+                                const void *TY, const int64_t *pairs, void *D, hipStream_t st)
+{
+    last_error().clear();
+    if (!plan) return fail(TWED_ERR_INVALID, "plan is NULL");
+    if (!X || !TX || !D) return fail(TWED_ERR_INVALID, "NULL array argument");
+    const BatchPlan &P = plan->p;
+    if (P.sym != (Y == nullptr) || (!P.sym && !TY) || (P.sym && TY))
+        return fail(TWED_ERR_INVALID, "Y / TY do not match the plan (NULL exactly when the plan is symmetric)");
+    if (P.list != (pairs != nullptr)) return fail(TWED_ERR_INVALID, "pairs given exactly when the plan has nPairs > 0");
+    return batch_enqueue(P, X, TX, Y, TY, pairs, D, st);
+}
+
+void twed_batch_plan_destroy(twed_batch_plan *plan) { delete plan; }
 
 const char *twed_status_string(twed_status s)
 {

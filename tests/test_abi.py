@@ -281,3 +281,21 @@ def test_dp_host_checks(L):
     assert dp(1) == WORKSPACE
     assert L.twed_dp_path(2, FAKE, 10, FAKE, 10, c.byref(prm1), -1, FAKE, FAKE, FAKE, None, 0, None) == INVALID
     assert L.twed_dp_path(2, FAKE, 10, FAKE, 10, c.byref(prm1), 0, FAKE, None, FAKE, None, 0, None) == INVALID
+
+
+def test_batch_plan_host_checks(L):
+    c = ctypes
+    prm = tw.make_params(dim=1)
+    off = np.array([0, 5, 9], np.int64)
+    bad = np.array([0, 5, 5], np.int64)
+    po = off.ctypes.data_as(c.POINTER(c.c_int64))
+    pb = bad.ctypes.data_as(c.POINTER(c.c_int64))
+    h = c.c_void_p()
+    assert L.twed_batch_plan_create(po, 2, None, 0, 0, c.byref(prm), None, 0, None) == INVALID   # no out
+    assert L.twed_batch_plan_create(po, 2, None, 0, 0, None, None, 0, c.byref(h)) == INVALID     # no params
+    assert L.twed_batch_plan_create(pb, 2, None, 0, 0, c.byref(prm), None, 0, c.byref(h)) == INVALID  # empty series
+    assert L.twed_batch_plan_create(po, 2, None, 0, -1, c.byref(prm), None, 0, c.byref(h)) == INVALID
+    assert L.twed_batch_plan_create(po, 2, None, 0, 0, c.byref(prm), None, 0, c.byref(h)) == WORKSPACE
+    assert not h.value
+    assert L.twed_batch_plan_run(None, FAKE, FAKE, None, None, None, FAKE, None) == INVALID
+    L.twed_batch_plan_destroy(None)

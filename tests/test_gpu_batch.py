@@ -196,3 +196,78 @@ def test_short_query_lane_mode_bitwise(prec):
         ref = oracle.get().pairs(rounded(q), rounded(tq), np.array([0, nq]), rounded(Y), rounded(col.T), col.off,
                                  np.array([(0, j) for j in range(col.count)]), 0.05, 0.7, p)
         assert max_rel(D, ref) <= {"f64": 1e-12, "f32": 1e-5, "f32_acc64": 1e-6}[prec]
+
+
+def _walks(rng, lens, dim):
+    xs = [rng.standard_normal((n, dim)).cumsum(0) for n in lens]
+    ts = [np.cumsum(rng.exponential(1.0, n)) for n in lens]
+    return np.concatenate(xs), np.concatenate(ts), np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+
+
+@pytest.mark.parametrize("case", ["sym_long_f32", "query_lane_f64", "pairs_acc64"])
+def test_batch_plan_graph_replay(case):
+    """A batch plan runs kernels only, so its run can be captured in a graph:
+    every replay, on fresh input values copied into the captured tensors and
+    with other library work and host synchronisation between replays, is
+    bitwise the eager twed_batch result on the same values."""
+    rng = np.random.default_rng({"sym_long_f32": 5, "query_lane_f64": 6, "pairs_acc64": 7}[case])
+    prec, dim = {"sym_long_f32": ("f32", 1), "query_lane_f64": ("f64", 3), "pairs_acc64": ("f32_acc64", 2)}[case]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    kw = dict(nu=0.02, lam=0.6, p=2.0 if dim > 1 else 1.0, precision=prec)
+    if case == "sym_long_f32":
+        # two series longer than one wave's strip: the single-pair sweeps
+        lens_x = list(rng.integers(20, 300, 30)) + [1500, 1300]
+        lens_y, n_pairs = None, 0
+    elif case == "query_lane_f64":
+        lens_x, lens_y, n_pairs = [23], list(rng.integers(5, 200, 150)), 0
+    else:
+        lens_x, lens_y, n_pairs = list(rng.integers(10, 120, 19)), list(rng.integers(10, 300, 11)), 257
+    variants = []
+    for _ in range(4):
+        X, TX, offX = _walks(rng, lens_x, dim)
+        Y, TY, offY = _walks(rng, lens_y, dim) if lens_y is not None else (None, None, None)
+        variants.append((X, TX, Y, TY))
+    pl = None
+    if n_pairs:
+        pl = torch.as_tensor(np.stack([rng.integers(0, len(lens_x), n_pairs), rng.integers(0, len(lens_y), n_pairs)],
+                                      axis=1).astype(np.int64), device="cuda")
+
+    def eager(v):
+        X, TX, Y, TY = v
+        return tw.twed_batch(f(X), f(TX), offX, None if Y is None else f(Y), None if TY is None else f(TY),
+                             offY, pairs=pl, **kw)
+
+    say(f"batch plan {case}: eager results")
+    want = [eager(v).cpu().numpy() for v in variants]
+    other = synth.batch_collection(9, 5, 200, seed=77)
+    oX, oT = to_dev(other, prec if prec == "f64" else "f32")
+    other_want = tw.twed_batch(oX, oT, other.off, precision=prec).cpu().numpy()
+
+    plan = tw.BatchPlan(offX, offY, n_pairs=n_pairs, dim=dim, nu=kw["nu"], lam=kw["lam"], p=kw["p"],
+                        precision=prec)
+    X0, TX0, Y0, TY0 = variants[0]
+    bX, bTX = f(X0), f(TX0)
+    bY, bTY = (f(Y0), f(TY0)) if Y0 is not None else (None, None)
+    D = plan.output()
+    say(f"batch plan {case}: eager run")
+    plan.run(bX, bTX, bY, bTY, pairs=pl, D=D)
+    torch.cuda.synchronize()
+    assert np.array_equal(D.cpu().numpy(), want[0])
+    g = torch.cuda.CUDAGraph()
+    say(f"batch plan {case}: capture")
+    with torch.cuda.graph(g):
+        plan.run(bX, bTX, bY, bTY, pairs=pl, D=D)
+    for i in range(1, 4):
+        X, TX, Y, TY = variants[i]
+        bX.copy_(f(X)); bTX.copy_(f(TX))
+        if Y is not None:
+            bY.copy_(f(Y)); bTY.copy_(f(TY))
+        D.fill_(-1.0)
+        say(f"batch plan {case}: replay {i}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(D.cpu().numpy(), want[i]), (case, i)
+        o = tw.twed_batch(oX, oT, other.off, precision=prec).cpu().numpy()
+        assert np.array_equal(o, other_want)
+    plan.close()
