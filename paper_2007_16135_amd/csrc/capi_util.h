@@ -46,7 +46,8 @@ struct Carver {
     }
 };
 
-// Packed rows with kRowPad zero rows on each side; returns the row-0 pointer.
+// Packed rows with kRowPad zero rows before and kRowPadTail after; returns
+// the row-0 pointer.
 inline void *take_rows(Carver &c, Prec prec, int dimt, int64_t rows)
 {
     char *p = (char *)c.take(rows_bytes(prec, dimt, rows));

@@ -38,10 +38,10 @@ __global__ __launch_bounds__(256) void stage_kernel(const CT *__restrict__ X, co
     const int64_t gtid = (int64_t)blockIdx.y * gridDim.x * blockDim.x + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t gsize = (int64_t)gridDim.x * gridDim.y * blockDim.x;
     for (int64_t w = gtid; w < zero_words; w += gsize) zero_ptr[w] = 0u;
-    // kRowPad zero rows before and after the packed rows (read, never used,
-    // by sweep lanes that run ahead of or behind the series)
-    for (int64_t w = gtid; w < (int64_t)kRowPad * S; w += gsize) {
-        rows[w - (int64_t)kRowPad * S] = CT(0);
+    // kRowPad zero rows before and kRowPadTail after the packed rows (read,
+    // never used, by sweep lanes that run ahead of or behind the series)
+    for (int64_t w = gtid; w < (int64_t)kRowPadTail * S; w += gsize) {
+        if (w < (int64_t)kRowPad * S) rows[w - (int64_t)kRowPad * S] = CT(0);
         rows[total_rows * S + w] = CT(0);
     }
 

@@ -29,12 +29,16 @@ struct CostParams {
     int pm;    // PMode
 };
 
-// Zero rows kept before and after every packed row buffer.
+// Zero rows kept before and after every packed row buffer.  A sweep lane l
+// reads row t - l at step t (t < n + 64), and the pair sweep prefetches rows
+// up to kMaxRowAhead steps early, so the buffer ends with that many more.
 constexpr int kRowPad = 64;
+constexpr int kMaxRowAhead = 8;
+constexpr int kRowPadTail = kRowPad + kMaxRowAhead;
 // Bytes of a packed row buffer holding `rows` rows plus its padding.
 inline size_t rows_bytes(Prec prec, int dimt, int64_t rows)
 {
-    return (size_t)(rows + 2 * kRowPad) * (size_t)row_stride(prec, dimt) * cost_size(prec);
+    return (size_t)(rows + kRowPad + kRowPadTail) * (size_t)row_stride(prec, dimt) * cost_size(prec);
 }
 
 // Writes packed rows (zero pad row first) and deletion costs for nSeries

@@ -127,7 +127,8 @@ constexpr bool kStripCompiled = DIMT <= 16 || K <= 2;
 // same two ways to the next strip.
 //
 // rowsA points at row 0 of A and must stay readable from row -64 to row
-// nA + 64 (the staging pads the buffer): lanes that have not started yet, or
+// nA + 63 + the prefetch distance (the staging pads the buffer with kRowPad
+// rows before and kRowPadTail after): lanes that have not started yet, or
 // have finished, read rows outside 1..nA and compute values nobody uses, so
 // the row address needs no clamp.
 //
@@ -207,8 +208,12 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     // Rows of A are loaded kAhead steps before their use: one step of 64*K
     // columns hides the load behind K cells of work, which is enough for
     // wide strips; narrow strips of small samples keep a ring of kAhead + 1
-    // rows (kAhead + 1 divides every sub-chunk of 8, 16 or 32 steps).
-    constexpr int kAhead = (K <= 2 && DIMT <= 8) ? 3 : 1;
+    // rows (kAhead + 1 divides every sub-chunk of 8, 16 or 32 steps); one
+    // column per lane of 4-byte samples hides it behind 7 steps.
+    constexpr int kAhead = (K == 1 && sizeof(CT) == 4 && DIMT <= 8) ? 7 : (K <= 2 && DIMT <= 8) ? 3 : 1;
+    // lane 0 prefetches up to row nA + 63 + kAhead: inside the zero rows
+    // that end every packed buffer
+    static_assert(kWave - 1 + kAhead <= kRowPadTail, "row prefetch runs past the buffer padding");
     Row<CT, DIMT> cur, nxt;
     Row<CT, DIMT> ring[kAhead + 1];
     if constexpr (kAhead == 1) {
