@@ -287,7 +287,8 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
  * also clears the work ticket, the sweeps, the mirror and the widening), so
  * a caller can capture it in a HIP graph and replay it; X, TX, Y, TY, pairs
  * and D as for twed_batch, with the planned shapes (Y, TY NULL exactly for a
- * symmetric plan, pairs given exactly for a pair-list plan).  Runs on one
+ * symmetric plan, pairs given exactly for a pair-list plan; Y and TY may
+ * also be NULL for a plan whose Y twed_batch_plan_stage_y staged).  Runs on one
  * plan must not overlap: they share the workspace.  The plan is a host
  * object; twed_batch_plan_destroy frees it (not the workspace). */
 typedef struct twed_batch_plan twed_batch_plan;
@@ -295,6 +296,13 @@ typedef struct twed_batch_plan twed_batch_plan;
 twed_status twed_batch_plan_create(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY,
                                    int64_t nPairs, const twed_params *prm,
                                    void *workspace, size_t ws_bytes, twed_batch_plan **plan);
+
+/* Stages Y, TY (the planned second collection) into the plan's workspace on
+ * `stream`.  After it, twed_batch_plan_run with Y == TY == NULL reuses those
+ * rows instead of staging Y again: a fixed collection queried many times is
+ * packed once.  The staged rows stay valid until the next stage call or a
+ * run that passes Y.  Symmetric plans: TWED_ERR_INVALID. */
+twed_status twed_batch_plan_stage_y(twed_batch_plan *plan, const void *Y, const void *TY, hipStream_t stream);
 
 twed_status twed_batch_plan_run(const twed_batch_plan *plan, const void *X, const void *TX,
                                 const void *Y, const void *TY, const int64_t *pairs, void *D,

@@ -22,7 +22,7 @@ ALGOS = {"auto": 0, "wavefront": 1, "diagonal": 2}
 EXPORTS = [
     "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_matrix",
     "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
-    "twed_batch_plan_create", "twed_batch_plan_run", "twed_batch_plan_destroy",
+    "twed_batch_plan_create", "twed_batch_plan_run", "twed_batch_plan_destroy", "twed_batch_plan_stage_y",
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
     "twed_pair_tune", "twed_tune_clear",
     "twed_pair_tile_workspace_size", "twed_pair_tile", "twed_pair_path_workspace_size", "twed_pair_path",
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     L.twed_batch_plan_create.restype = ctypes.c_int
     L.twed_batch_plan_run.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.twed_batch_plan_run.restype = ctypes.c_int
+    L.twed_batch_plan_stage_y.argtypes = [_vp, _vp, _vp, _vp]
+    L.twed_batch_plan_stage_y.restype = ctypes.c_int
     L.twed_batch_plan_destroy.argtypes = [_vp]
     L.twed_batch_plan_destroy.restype = None
     L.twed_pair_tune.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, ctypes.c_size_t, _vp,
@@ -497,6 +499,15 @@ class BatchPlan:
         torch = _torch()
         shape = (self.n_pairs,) if self.n_pairs > 0 else (self.nX, self.nY)
         return torch.empty(shape, dtype=output_dtype(self.precision), device=self.ws.device)
+
+    def stage_y(self, Y, TY, stream=None):
+        """Packs the second collection once; run() without Y then reuses it."""
+        dt = input_dtype(self.precision)
+        Y2 = Y if Y.dim() == 2 else Y.reshape(-1, 1)
+        _dev(Y2, dt, "Y"); _dev(TY, dt, "TY")
+        if Y2.shape[1] != self.dim:
+            raise ValueError("Y has a different dimension than the plan")
+        _check(load_library().twed_batch_plan_stage_y(self._h, Y2.data_ptr(), TY.data_ptr(), _stream(stream)))
 
     def run(self, X, TX, Y=None, TY=None, pairs=None, D=None, stream=None):
         torch = _torch()

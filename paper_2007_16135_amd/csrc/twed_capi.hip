@@ -337,6 +337,7 @@ struct BatchPlan {
     std::vector<int32_t> order;       // longest-first order (symmetric)
     int64_t nX, nY, maxX, maxY, totX, totY, nPairs;
     bool sym, list;
+    bool y_staged = false;  // rows of Y staged by twed_batch_plan_stage_y
 };
 
 twed_status batch_prepare(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY, bool sym, bool list,
@@ -415,7 +416,9 @@ twed_status batch_upload(const BatchPlan &P, hipStream_t st, bool sync)
 }
 
 // Kernels only: staging (which also clears the work ticket), the sweeps, the
-// mirror of the symmetric case and the widening of TWED_AUTO results.
+// mirror of the symmetric case and the widening of TWED_AUTO results.  With
+// Y == NULL in the rectangular and pair-list cases the rows of Y staged
+// earlier are used as they are.
 twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, const void *Y, const void *TY,
                           const int64_t *pairs, void *D, hipStream_t st)
 {
@@ -435,7 +438,7 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
     e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, totX + nX, L.rowsX,
                      (uint32_t *)L.zero, 1, st);
     if (e != hipSuccess) return fail_hip(e, "staging launch");
-    if (!sym) {
+    if (!sym && Y) {
         e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, totY + nY, L.rowsY, nullptr, 0,
                          st);
         if (e != hipSuccess) return fail_hip(e, "staging launch");
@@ -720,10 +723,26 @@ twed_status twed_batch_plan_run(const twed_batch_plan *plan, const void *X, cons
     if (!plan) return fail(TWED_ERR_INVALID, "plan is NULL");
     if (!X || !TX || !D) return fail(TWED_ERR_INVALID, "NULL array argument");
     const BatchPlan &P = plan->p;
-    if (P.sym != (Y == nullptr) || (!P.sym && !TY) || (P.sym && TY))
-        return fail(TWED_ERR_INVALID, "Y / TY do not match the plan (NULL exactly when the plan is symmetric)");
+    if ((Y == nullptr) != (TY == nullptr)) return fail(TWED_ERR_INVALID, "Y and TY must both be given or both NULL");
+    if (P.sym && Y) return fail(TWED_ERR_INVALID, "a symmetric plan takes no Y");
+    if (!P.sym && !Y && !P.y_staged)
+        return fail(TWED_ERR_INVALID, "Y is NULL but twed_batch_plan_stage_y has not staged it");
     if (P.list != (pairs != nullptr)) return fail(TWED_ERR_INVALID, "pairs given exactly when the plan has nPairs > 0");
     return batch_enqueue(P, X, TX, Y, TY, pairs, D, st);
+}
+
+twed_status twed_batch_plan_stage_y(twed_batch_plan *plan, const void *Y, const void *TY, hipStream_t st)
+{
+    last_error().clear();
+    if (!plan) return fail(TWED_ERR_INVALID, "plan is NULL");
+    if (!Y || !TY) return fail(TWED_ERR_INVALID, "NULL array argument");
+    BatchPlan &P = plan->p;
+    if (P.sym) return fail(TWED_ERR_INVALID, "a symmetric plan takes no Y");
+    const hipError_t e = launch_stage(P.prec, P.cp, Y, TY, (const int64_t *)P.L.offY, P.nY, 0, P.maxY,
+                                      P.totY + P.nY, P.L.rowsY, nullptr, 0, st);
+    if (e != hipSuccess) return fail_hip(e, "staging launch");
+    P.y_staged = true;
+    return TWED_OK;
 }
 
 void twed_batch_plan_destroy(twed_batch_plan *plan) { delete plan; }

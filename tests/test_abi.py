@@ -298,4 +298,5 @@ def test_batch_plan_host_checks(L):
     assert L.twed_batch_plan_create(po, 2, None, 0, 0, c.byref(prm), None, 0, c.byref(h)) == WORKSPACE
     assert not h.value
     assert L.twed_batch_plan_run(None, FAKE, FAKE, None, None, None, FAKE, None) == INVALID
+    assert L.twed_batch_plan_stage_y(None, FAKE, FAKE, None) == INVALID
     L.twed_batch_plan_destroy(None)

@@ -271,3 +271,42 @@ def test_batch_plan_graph_replay(case):
         o = tw.twed_batch(oX, oT, other.off, precision=prec).cpu().numpy()
         assert np.array_equal(o, other_want)
     plan.close()
+
+
+@pytest.mark.parametrize("prec,dim,nq", [("f64", 28, 28), ("f32", 3, 150)])
+def test_batch_plan_staged_collection(prec, dim, nq):
+    """A collection staged once by the plan serves many queries: runs without
+    Y (eager and replayed from a graph, with new query values each time) are
+    bitwise the eager twed_batch result with Y passed; a run without Y before
+    staging is refused on the host.  nq = 28: one short query (lane per pair);
+    nq = 150: longer than a lane-mode query (wave per pair)."""
+    rng = np.random.default_rng(90 + dim)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    lens_y = list(rng.integers(10, 60, 97))
+    Y, TY, offY = _walks(rng, lens_y, dim)
+    offX = np.array([0, nq], np.int64)
+    queries = [_walks(rng, [nq], dim)[:2] for _ in range(4)]
+    kw = dict(nu=0.01, lam=0.4, p=2.0, precision=prec)
+    want = [tw.twed_batch(f(q), f(t), offX, f(Y), f(TY), offY, **kw).cpu().numpy() for q, t in queries]
+    plan = tw.BatchPlan(offX, offY, dim=dim, nu=0.01, lam=0.4, p=2.0, precision=prec)
+    bX, bTX = f(queries[0][0]), f(queries[0][1])
+    D = plan.output()
+    with pytest.raises(tw.TwedError):
+        plan.run(bX, bTX, D=D)
+    say(f"staged collection {prec} dim {dim}: stage and eager run")
+    plan.stage_y(f(Y), f(TY))
+    plan.run(bX, bTX, D=D)
+    torch.cuda.synchronize()
+    assert np.array_equal(D.cpu().numpy(), want[0])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(bX, bTX, D=D)
+    for i in range(1, 4):
+        bX.copy_(f(queries[i][0])); bTX.copy_(f(queries[i][1]))
+        D.fill_(-1.0)
+        say(f"staged collection {prec} dim {dim}: replay {i}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(D.cpu().numpy(), want[i]), i
+    plan.close()
