@@ -180,9 +180,15 @@ PathGeometry path_geometry(int rec, const twed_params *prm, int64_t nA, int64_t 
 // Edit and indel distances start from finite row 0 / column 0 (i, i).
 bool finite_edges(int rec) { return rec == kRecEdit || rec == kRecIndel; }
 
+// Blocks recomputed with moves at once: the block the walk is in and the
+// three it can leave into (up, left, up-left), each in its own slot.
+constexpr int kPathSlots = 4;
+
 struct PathLayout {
     SweepBuffers b;
-    void *ckrow, *ckcol, *dirs, *row0, *col0;
+    SweepBuffers slot[kPathSlots];  // boundary, flags, dummy and result of one block sweep
+    void *dirs[kPathSlots];
+    void *ckrow, *ckcol, *row0, *col0;
     int64_t *st;
     size_t total;
 };
@@ -201,11 +207,50 @@ PathLayout path_layout(char *base, int rec, const twed_params *prm, int64_t nA, 
     L.ckrow = c.take((size_t)g.nr * (size_t)(nB + 1) * kCell);
     L.ckcol = c.take((size_t)g.nc * (size_t)(nA + 1) * kCell);
     const int64_t Wb = 64 * (int64_t)g.blk.K;
-    const int64_t strips = (std::min(g.Wc, nB) + Wb - 1) / Wb;
-    L.dirs = c.take((size_t)strips * (size_t)(std::min(g.H, nA) + 64) * (size_t)Wb);
+    const int64_t bh = std::min(g.H, nA), bw = std::min(g.Wc, nB);
+    const int64_t strips = (bw + Wb - 1) / Wb;
+    for (int k = 0; k < kPathSlots; ++k) {
+        SweepBuffers &u = L.slot[k];
+        u.rowsA = L.b.rowsA;
+        u.rowsB = L.b.rowsB;
+        u.bnd = c.take((size_t)2 * (size_t)(bh + 1) * kCell);
+        u.zero_words = (bw + 63) / 64 + kTailWords;
+        u.flags = (uint32_t *)c.take((size_t)u.zero_words * 4);
+        u.dummy = c.take(kDummyCells * kCell);
+        u.tmp = c.take(8);
+        L.dirs[k] = c.take((size_t)strips * (size_t)(bh + 64) * (size_t)Wb);
+    }
     L.total = c.used;
     return L;
 }
+
+// Side streams and events of the backward pass; the destructor waits for
+// their work (speculative block sweeps may still run) before releasing them.
+struct PathStreams {
+    hipStream_t s[kPathSlots] = {};
+    hipEvent_t done[kPathSlots] = {};
+    hipEvent_t fwd = nullptr;
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreateWithFlags(&fwd, hipEventDisableTiming);
+        for (int k = 0; k < kPathSlots && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&s[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&done[k], hipEventDisableTiming);
+        }
+        return e;
+    }
+    ~PathStreams()
+    {
+        for (int k = 0; k < kPathSlots; ++k) {
+            if (s[k]) {
+                (void)hipStreamSynchronize(s[k]);
+                (void)hipStreamDestroy(s[k]);
+            }
+            if (done[k]) (void)hipEventDestroy(done[k]);
+        }
+        if (fwd) (void)hipEventDestroy(fwd);
+    }
+};
 
 // The path of one pair under recurrence `rec` (A/TA/B/TB as staged by
 // twed_pair; TA, TB null for the siblings).  Runs after argument checks.
@@ -244,10 +289,47 @@ twed_status path_impl(int rec, const void *A, const void *TA, int64_t nA, const 
     t.ck_cols = (int)g.Wc;
     s = run_tile(rec, prec, cp, g.fwd, b.rowsA, b.rowsB, nA, nB, b, t, out, st);
     if (s != TWED_OK) return s;
-    // backwards, block by block: sweep the block again recording moves, walk it
+    // Backwards, block by block: sweep the block again recording moves, walk
+    // it.  While the walk runs on the caller's stream, the blocks it can
+    // leave into are swept on side streams, so that the next walk finds its
+    // moves ready: the sweep of a block (latency-bound one-column strips on
+    // a few CUs) then overlaps the walk of the one before.
     const int64_t cap = nA + nB + 1;
     TRY(launch_walk_init(L.st, nA, nB, st), "walk set-up");
     const size_t rb = row_bytes(prec, dimt_for(prm->dim));
+    PathStreams ps;
+    TRY(ps.create(), "stream set-up");
+    TRY(hipEventRecord(ps.fwd, st), "event record");
+    for (int k = 0; k < kPathSlots; ++k) TRY(hipStreamWaitEvent(ps.s[k], ps.fwd, 0), "stream wait");
+    int64_t held[kPathSlots][2];
+    for (int k = 0; k < kPathSlots; ++k) held[k][0] = held[k][1] = -1;
+    // sweeps block (br, bc) with moves into slot k on side stream k
+    auto sweep_block = [&](int k, int64_t br, int64_t bc) -> twed_status {
+        const int64_t r0 = br * g.H, r1 = std::min(r0 + g.H, nA);
+        const int64_t c0 = bc * g.Wc, c1 = std::min(c0 + g.Wc, nB);
+        const SweepBuffers &sb = L.slot[k];
+        hipError_t e2 = launch_zero32(sb.flags, sb.zero_words, ps.s[k]);
+        if (e2 != hipSuccess) return fail_hip(e2, "flag reset");
+        TileArgs u{};
+        u.dummy = sb.dummy;
+        if (br > 0)
+            u.top = (const char *)L.ckrow + ((size_t)(br - 1) * (size_t)(nB + 1) + (size_t)c0) * kCell;
+        else if (L.row0)
+            u.top = (const char *)L.row0 + (size_t)c0 * kCell;
+        if (bc > 0)
+            u.left = (const char *)L.ckcol + ((size_t)(bc - 1) * (size_t)(nA + 1) + (size_t)r0) * kCell;
+        else if (L.col0)
+            u.left = (const char *)L.col0 + (size_t)r0 * kCell;
+        u.dirs = (uint8_t *)L.dirs[k];
+        const twed_status s2 = run_tile(rec, prec, cp, g.blk, (const char *)b.rowsA + r0 * rb,
+                                        (const char *)b.rowsB + c0 * rb, r1 - r0, c1 - c0, sb, u, sb.tmp, ps.s[k]);
+        if (s2 != TWED_OK) return s2;
+        e2 = hipEventRecord(ps.done[k], ps.s[k]);
+        if (e2 != hipSuccess) return fail_hip(e2, "event record");
+        held[k][0] = br;
+        held[k][1] = bc;
+        return TWED_OK;
+    };
     int64_t hst[4] = {0, 0, 0, 0};
     const int64_t max_blocks = g.nr + g.nc + 3;
     for (int64_t it = 0;; ++it) {
@@ -257,27 +339,45 @@ twed_status path_impl(int rec, const void *A, const void *TA, int64_t nA, const 
         if (hst[3] != 0 || it > max_blocks || hst[0] < 1 || hst[1] < 1)
             return fail(TWED_ERR_DEVICE, "the path could not be followed (non-finite distance or a timed-out sweep)");
         const int64_t br = (hst[0] - 1) / g.H, bc = (hst[1] - 1) / g.Wc;
+        // this block first, then the up, left and up-left neighbours
+        int64_t want[kPathSlots][2];
+        int nw = 0;
+        want[nw][0] = br, want[nw][1] = bc, ++nw;
+        if (br > 0) want[nw][0] = br - 1, want[nw][1] = bc, ++nw;
+        if (bc > 0) want[nw][0] = br, want[nw][1] = bc - 1, ++nw;
+        if (br > 0 && bc > 0) want[nw][0] = br - 1, want[nw][1] = bc - 1, ++nw;
+        auto slot_of = [&](int64_t qr, int64_t qc) {
+            for (int k = 0; k < kPathSlots; ++k)
+                if (held[k][0] == qr && held[k][1] == qc) return k;
+            return -1;
+        };
+        // slots whose block is not wanted may be overwritten (slot k's
+        // earlier sweep is ordered before the new one on stream k, and every
+        // walk that read it has finished: the caller's stream was synchronised)
+        bool keep[kPathSlots] = {};
+        for (int w = 0; w < nw; ++w) {
+            const int k = slot_of(want[w][0], want[w][1]);
+            if (k >= 0) keep[k] = true;
+        }
+        for (int w = 0; w < nw; ++w) {
+            if (slot_of(want[w][0], want[w][1]) >= 0) continue;
+            int k = 0;
+            while (keep[k]) ++k;  // nw <= kPathSlots, so a free slot exists
+            keep[k] = true;
+            if ((s = sweep_block(k, want[w][0], want[w][1])) != TWED_OK) return s;
+        }
+        const int kc = slot_of(br, bc);
         const int64_t r0 = br * g.H, r1 = std::min(r0 + g.H, nA);
         const int64_t c0 = bc * g.Wc, c1 = std::min(c0 + g.Wc, nB);
-        TRY(launch_zero32(b.flags, b.zero_words, st), "flag reset");
-        TileArgs u{};
-        u.dummy = b.dummy;
-        if (br > 0)
-            u.top = (const char *)L.ckrow + ((size_t)(br - 1) * (size_t)(nB + 1) + (size_t)c0) * kCell;
-        else if (L.row0)
-            u.top = (const char *)L.row0 + (size_t)c0 * kCell;
-        if (bc > 0)
-            u.left = (const char *)L.ckcol + ((size_t)(bc - 1) * (size_t)(nA + 1) + (size_t)r0) * kCell;
-        else if (L.col0)
-            u.left = (const char *)L.col0 + (size_t)r0 * kCell;
-        u.dirs = (uint8_t *)L.dirs;
-        s = run_tile(rec, prec, cp, g.blk, (const char *)b.rowsA + r0 * rb, (const char *)b.rowsB + c0 * rb,
-                     r1 - r0, c1 - c0, b, u, b.tmp, st);
-        if (s != TWED_OK) return s;
-        TRY(launch_walk((const uint8_t *)L.dirs, r0, c0, r1 - r0, c1 - c0, g.blk.K, (r1 - r0) + 64, L.st, path, cap,
-                        finite_edges(rec), st),
+        TRY(hipStreamWaitEvent(st, ps.done[kc], 0), "stream wait");
+        TRY(launch_walk((const uint8_t *)L.dirs[kc], r0, c0, r1 - r0, c1 - c0, g.blk.K, (r1 - r0) + 64, L.st, path,
+                        cap, finite_edges(rec), st),
             "walk");
     }
+    // later work on the caller's stream (and its reuse of the workspace)
+    // stays behind speculative sweeps still running
+    for (int k = 0; k < kPathSlots; ++k)
+        if (held[k][0] >= 0) TRY(hipStreamWaitEvent(st, ps.done[k], 0), "stream wait");
     TRY(launch_order(L.st, path, path_len, cap, st), "path order");
 #undef TRY
     return TWED_OK;
