@@ -193,7 +193,9 @@ twed_status twed_pair_tile(const void *A, const void *TA, int64_t nA,
  * is swept again recording one byte per cell; block == 0 means 4096.
  * Precision TWED_F64 or TWED_F32_ACC64.  The call reads the walk's position
  * between blocks, so it synchronises `stream` and returns when the path is
- * complete.  Errors as twed_pair_tile, plus TWED_ERR_INVALID for NULL
+ * complete; the blocks next to the one being walked are swept meanwhile on
+ * non-blocking streams the call creates, orders after `stream` and waits
+ * for before it returns.  Errors as twed_pair_tile, plus TWED_ERR_INVALID for NULL
  * outputs or block < 0, and TWED_ERR_DEVICE when no finite path exists. */
 size_t twed_pair_path_workspace_size(int64_t nA, int64_t nB, const twed_params *prm, int64_t block);
 
