@@ -22,6 +22,23 @@ inline twed_status fail(twed_status s, const char *msg)
     return s;
 }
 
+// Runs the body of an entry point that allocates host memory (containers,
+// messages): an allocation failure becomes TWED_ERR_DEVICE instead of an
+// exception crossing the C ABI.
+template <typename F>
+inline twed_status no_throw(F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (...) {
+        try {
+            last_error() = "host allocation failed";
+        } catch (...) {
+        }
+        return TWED_ERR_DEVICE;
+    }
+}
+
 inline twed_status fail_hip(hipError_t e, const char *where)
 {
     last_error() = std::string(where) + ": " + hipGetErrorString(e);

@@ -416,9 +416,9 @@ size_t twed_knn_index_storage_size(const int64_t *offDB, int64_t nDB, const twed
     return index_layout(nullptr, nDB, total).total;
 }
 
-twed_status twed_knn_index_create(const void *DB, const void *TDB, const int64_t *offDB, int64_t nDB,
-                                  const float *params, const twed_params *prm, void *storage, size_t storage_bytes,
-                                  twed_knn_index **out)
+static twed_status twed_knn_index_create_body(const void *DB, const void *TDB, const int64_t *offDB, int64_t nDB,
+                                              const float *params, const twed_params *prm, void *storage, size_t storage_bytes,
+                                              twed_knn_index **out)
 {
     last_error().clear();
     if (!out) return fail(TWED_ERR_INVALID, "out is NULL");
@@ -450,6 +450,15 @@ twed_status twed_knn_index_create(const void *DB, const void *TDB, const int64_t
     ix->rows = L.rows;
     *out = ix;
     return TWED_OK;
+}
+
+twed_status twed_knn_index_create(const void *DB, const void *TDB, const int64_t *offDB, int64_t nDB,
+                                  const float *params, const twed_params *prm, void *storage, size_t storage_bytes,
+                                  twed_knn_index **out)
+{
+    return no_throw([&] {
+        return twed_knn_index_create_body(DB, TDB, offDB, nDB, params, prm, storage, storage_bytes, out);
+    });
 }
 
 size_t twed_knn_index_build_workspace_size(const twed_knn_index *ix)

@@ -564,9 +564,9 @@ twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA, const vo
     return pair_impl(A, TA, nA, B, TB, nB, prm, out, dp, workspace, ws_bytes, stream);
 }
 
-twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
-                           const twed_params *prm, void *workspace, size_t ws_bytes, hipStream_t st,
-                           int32_t *strip_k, int32_t *group)
+static twed_status twed_pair_tune_body(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                                       const twed_params *prm, void *workspace, size_t ws_bytes, hipStream_t st,
+                                       int32_t *strip_k, int32_t *group)
 {
     last_error().clear();
     twed_status s = check_params(prm);
@@ -635,6 +635,15 @@ twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA, const void
     return TWED_OK;
 }
 
+twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                           const twed_params *prm, void *workspace, size_t ws_bytes, hipStream_t st,
+                           int32_t *strip_k, int32_t *group)
+{
+    return no_throw([&] {
+        return twed_pair_tune_body(A, TA, nA, B, TB, nB, prm, workspace, ws_bytes, st, strip_k, group);
+    });
+}
+
 void twed_tune_clear(void)
 {
     std::lock_guard<std::mutex> lock(tune_mutex());
@@ -668,9 +677,9 @@ size_t twed_batch_workspace_size(const int64_t *offX, int64_t nX, const int64_t 
     return batch_layout(nullptr, totX, nX, maxX, totY, nY, maxY, sym, nOut, prm, prec).total;
 }
 
-twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64_t nX, const void *Y,
-                       const void *TY, const int64_t *offY, int64_t nY, const int64_t *pairs, int64_t nPairs,
-                       const twed_params *prm, void *D, void *workspace, size_t ws_bytes, hipStream_t st)
+static twed_status twed_batch_body(const void *X, const void *TX, const int64_t *offX, int64_t nX, const void *Y,
+                                   const void *TY, const int64_t *offY, int64_t nY, const int64_t *pairs, int64_t nPairs,
+                                   const twed_params *prm, void *D, void *workspace, size_t ws_bytes, hipStream_t st)
 {
     last_error().clear();
     if (!prm) return fail(TWED_ERR_INVALID, "params is NULL");
@@ -687,6 +696,15 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
     return batch_enqueue(P, X, TX, Y, TY, pairs, D, st);
 }
 
+twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64_t nX, const void *Y,
+                       const void *TY, const int64_t *offY, int64_t nY, const int64_t *pairs, int64_t nPairs,
+                       const twed_params *prm, void *D, void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    return no_throw([&] {
+        return twed_batch_body(X, TX, offX, nX, Y, TY, offY, nY, pairs, nPairs, prm, D, workspace, ws_bytes, st);
+    });
+}
+
 }  // extern "C"
 
 struct twed_batch_plan {
@@ -695,8 +713,8 @@ struct twed_batch_plan {
 
 extern "C" {
 
-twed_status twed_batch_plan_create(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY, int64_t nPairs,
-                                   const twed_params *prm, void *workspace, size_t ws_bytes, twed_batch_plan **out)
+static twed_status twed_batch_plan_create_body(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY, int64_t nPairs,
+                                               const twed_params *prm, void *workspace, size_t ws_bytes, twed_batch_plan **out)
 {
     last_error().clear();
     if (!out) return fail(TWED_ERR_INVALID, "out is NULL");
@@ -714,6 +732,14 @@ twed_status twed_batch_plan_create(const int64_t *offX, int64_t nX, const int64_
     }
     *out = plan;
     return TWED_OK;
+}
+
+twed_status twed_batch_plan_create(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY, int64_t nPairs,
+                                   const twed_params *prm, void *workspace, size_t ws_bytes, twed_batch_plan **out)
+{
+    return no_throw([&] {
+        return twed_batch_plan_create_body(offX, nX, offY, nY, nPairs, prm, workspace, ws_bytes, out);
+    });
 }
 
 twed_status twed_batch_plan_run(const twed_batch_plan *plan, const void *X, const void *TX, const void *Y,
