@@ -283,8 +283,8 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
  * caller keeps it allocated and untouched while the plan lives) and copies
  * the offsets and the longest-first order of the series into it with a
  * synchronous copy.  offY == NULL plans the symmetric matrix of X (nY is
- * then ignored);
- * nPairs > 0 plans a pair list of that length, nPairs == 0 the full matrix.
+ * then ignored); nPairs > 0 plans a pair list of that length (D then holds
+ * nPairs results), nPairs == 0 the full matrix.
  * twed_batch_plan_run then enqueues kernels only on `stream` (staging, which
  * also clears the work ticket, the sweeps, the mirror and the widening), so
  * a caller can capture it in a HIP graph and replay it; X, TX, Y, TY, pairs
@@ -292,7 +292,10 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
  * symmetric plan, pairs given exactly for a pair-list plan; Y and TY may
  * also be NULL for a plan whose Y twed_batch_plan_stage_y staged).  Runs on one
  * plan must not overlap: they share the workspace.  The plan is a host
- * object; twed_batch_plan_destroy frees it (not the workspace). */
+ * object; twed_batch_plan_destroy frees it (not the workspace).
+ * Errors: as twed_batch at creation; at a run, TWED_ERR_INVALID (on the
+ * host, before any launch) for a NULL plan or arguments that do not match
+ * the plan. */
 typedef struct twed_batch_plan twed_batch_plan;
 
 twed_status twed_batch_plan_create(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY,
