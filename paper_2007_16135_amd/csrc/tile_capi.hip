@@ -379,6 +379,8 @@ twed_status path_impl(int rec, const void *A, const void *TA, int64_t nA, const 
     for (int k = 0; k < kPathSlots; ++k)
         if (held[k][0] >= 0) TRY(hipStreamWaitEvent(st, ps.done[k], 0), "stream wait");
     TRY(launch_order(L.st, path, path_len, cap, st), "path order");
+    // the path and its length are complete when the call returns
+    TRY(hipStreamSynchronize(st), "path order");
 #undef TRY
     return TWED_OK;
 }

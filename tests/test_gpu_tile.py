@@ -196,3 +196,23 @@ def test_high_dimensional_tiles_and_paths(prec):
         close(bot.cpu().numpy()[:, 0], DP[r1, c0:c1 + 1], RTOL[prec])
         close(rig.cpu().numpy()[:, 1], X[r0:r1 + 1, c1], RTOL[prec])
         _path_case(90 + dim, 260, 300, dim, prec, 64)
+
+
+def test_path_on_a_side_stream():
+    """The path call on a stream other than the current one (its block sweeps
+    run on streams of its own, ordered after the caller's): the same distance
+    and path as on the current stream, complete when the call returns."""
+    c = synth.random_pair(81, 82, 700, 650, 3, irregular=True, nu=0.02, lam=0.5, p=2.0)
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    A, TA, B, TB = f(c.A), f(c.TA), f(c.B), f(c.TB)
+    say("path on the current stream")
+    d0, p0 = tw.twed_pair_path(A, TA, B, TB, c.nu, c.lam, c.p, "f64", block=64)
+    d0, p0 = float(d0.item()), p0.cpu().numpy()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    say("path on a side stream")
+    d1, p1 = tw.twed_pair_path(A, TA, B, TB, c.nu, c.lam, c.p, "f64", block=64, stream=s)
+    with torch.cuda.stream(s):
+        d1, p1 = float(d1.item()), p1.cpu().numpy()
+    assert d1 == d0
+    assert np.array_equal(p1, p0)
