@@ -40,6 +40,19 @@ OPS_PER_CELL_8D_L2_ACC64 = 29
 #   match add, two deletion adds, one three-way min (v_min3_f32 is a single
 #   full-rate instruction), X add = 8
 OPS_PER_CELL_1D_L1_F32 = 8
+#   3-D L2: 3 sub + 1 mul + 2 fma + sqrt (4) = 10; time sub + fma = 2; then
+#   FP64 accumulators: match add, two deletion adds, two min, X add = 6 (18);
+#   FP32 accumulators: the three-way min is one v_min3_f32 (17)
+OPS_PER_CELL_3D_L2_F64 = 18
+OPS_PER_CELL_3D_L2_F32 = 17
+#   1-D L1 in f64: value sub, time sub, fma; match add, two deletion adds,
+#   two min (no three-way f64 min), X add = 9
+OPS_PER_CELL_1D_L1_F64 = 9
+
+# The paper's single-pair timings (table "Raw Time to Solution", 1-D FP64,
+# most likely a P100; cuTWED_dev = device-resident inputs), seconds by N.
+PAPER_CUTWED_DEV_S = {1048576: 211.51, 524288: 54.084, 262144: 13.827, 131072: 3.6344, 65536: 0.8571,
+                      32768: 0.2851, 16384: 0.1140, 8192: 0.0499, 4096: 0.0243, 2048: 0.0118, 1024: 0.0059}
 
 
 def log(*a):
@@ -81,9 +94,13 @@ def parse():
     ap.add_argument("--rn-all", action="store_true", help="also time the 60000 x 60000 R^28 all-pairs matrix")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (counter calibration)")
-    ap.add_argument("--knn", action="store_true",
-                    help="also run the learned k-NN measurement (off by default: its 1e5-series "
-                         "database run faulted the GPU once and the cause is not yet found)")
+    ap.add_argument("--knn", action="store_true", help="also run the learned k-NN measurement")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the on-device VALU / HBM rate probes")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 3-D n=1e5 pair")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the headline pair")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped workloads")
+    ap.add_argument("--cpu-pairs", type=int, default=20000,
+                    help="pairs of the all-pairs batch timed on all host cores with the oracle")
     ap.add_argument("--knn-db", type=int, default=100_000, help="k-NN database size")
     ap.add_argument("--knn-queries", type=int, default=10_000, help="k-NN queries timed")
     ap.add_argument("--knn-truth", type=int, default=1000,
@@ -107,6 +124,55 @@ def time_steps(fn, steps, warmup, torch):
     wall = time.perf_counter() - t0
     per = [a.elapsed_time(b) / 1e3 for a, b in ev]
     return wall, per
+
+
+def measure_peaks(torch, dev):
+    """Achievable VALU lane-operation rates (twed_probe_valu: eight independent
+    chains per lane, FP32 / FP64 FMA and add+min) and the HBM rate of a plain
+    device copy, measured on this GPU."""
+    import ctypes
+    from paper_2007_16135_amd import binding as Bd
+    L = Bd.load_library()
+    props = torch.cuda.get_device_properties(dev)
+    cus = props.multi_processor_count
+    waves = cus * 4 * 8  # eight waves per SIMD
+    sink = torch.empty(waves * 64, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    out = {"compute_units": cus}
+    names = {0: "f32_fma", 1: "f32_add_min", 2: "f64_fma", 3: "f64_add_min"}
+    for kind, name in names.items():
+        iters = 60000 if kind in (0, 2) else 30000
+        ops = ctypes.c_double()
+        best = None
+        for _ in range(4):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            Bd._check(L.twed_probe_valu(kind, waves, iters, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ops),
+                                         ctypes.c_void_p(stream.cuda_stream)))
+            b.record(stream)
+            b.synchronize()
+            t = a.elapsed_time(b) / 1e3
+            best = t if best is None else min(best, t)
+        out[name + "_T_lane_op_s"] = round(ops.value / best / 1e12, 3)
+    n = 1 << 30  # 4 GiB copy: read 4 GiB + write 4 GiB
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+        b.synchronize()
+        t = a.elapsed_time(b) / 1e3
+        best = t if best is None else min(best, t)
+    out["hbm_copy_GB_s"] = round(2 * 4 * n / best / 1e9, 1)
+    del src, dst, sink
+    torch.cuda.empty_cache()
+    out["valu_lane_op_peak_derived_T"] = round(VALU_PEAK_TOPS, 3)
+    return out
 
 
 def knn_bench(args, torch, tw, synth, dev, time_steps):
@@ -196,6 +262,137 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
     return out
 
 
+def c2_bench(torch, tw, synth, dev, peaks):
+    """3-D walks n = m = 1e5 (seeds 2/3, irregular times, nu = 0.01,
+    lambda = 0.5, L2): FP64 and FP32 runs, each against the FP64 oracle value
+    of the same inputs (tests/golden/oracle_values.json, written by the oracle
+    alone)."""
+    gold = {c["name"]: c["value"] for c in json.load(open(os.path.join(ROOT, "tests", "golden",
+                                                                       "oracle_values.json")))["cases"]}
+    c = synth.single_pair_3d(100_000)
+    n = 100_000
+    cells = float(n) * n
+    out = {"workload": "single pair, 3-D random walks n=m=100000, irregular Exp(1) timestamps, nu=0.01, "
+                       "lambda=0.5, L2", "cells_per_step": cells}
+    for prec, key, ops, gname in (("f64", "fp64", OPS_PER_CELL_3D_L2_F64, "walk3d_n100000"),
+                                  ("f32", "fp32", OPS_PER_CELL_3D_L2_F32, "walk3d_n100000_f32")):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+        A, TA, B, TB = t(c.A), t(c.TA), t(c.B), t(c.TB)
+        prm = tw.make_params(c.nu, c.lam, c.p, 3, prec)
+        ws = torch.empty(max(tw.twed_pair_workspace_size(n, n, prm), 256), dtype=torch.uint8, device=dev)
+        res = torch.empty(1, dtype=torch.float64 if prec == "f64" else torch.float32, device=dev)
+        wall, per = time_steps(lambda: tw.twed_pair(A, TA, B, TB, c.nu, c.lam, c.p, prec, out=res, workspace=ws),
+                               5, 2, torch)
+        k = float(np.median(per))
+        v = float(res.item())
+        entry = {"ms": round(k * 1e3, 3), "GCUPS": round(cells / k / 1e9, 3), "result": v,
+                 "oracle": gold[gname], "rel_err_vs_oracle": abs(v - gold[gname]) / gold[gname],
+                 "ops_per_cell": ops,
+                 "roofline_frac": round(ops * cells / k / 1e12 / VALU_PEAK_TOPS, 4)}
+        if peaks:
+            rate = peaks["f64_add_min_T_lane_op_s"] if prec == "f64" else peaks["f32_add_min_T_lane_op_s"]
+            entry["frac_of_measured_peak"] = round(ops * cells / k / 1e12 / rate, 4)
+        out[key] = entry
+        del A, TA, B, TB, ws
+    log(f"pair 3d n=1e5: {out}")
+    return out
+
+
+def batch_checks(torch, tw, col, X, T, D, dev, samples=256):
+    """The timed FP32 matrix against the FP64 oracle on sampled entries, and
+    an FP64 GPU run of the same batch (inputs: the FP32 values widened)
+    against which every FP32 entry's error is stated."""
+    import oracle
+    n = col.count
+    Dh = D.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(99)
+    i = rng.integers(0, n, samples)
+    j = rng.integers(0, n - 1, samples)
+    j = j + (j >= i)
+    X64 = col.X.astype(np.float32).astype(np.float64)
+    T64 = col.T.astype(np.float32).astype(np.float64)
+    ref = oracle.get().pairs(X64, T64, col.off, X64, T64, col.off, np.stack([i, j], 1), 1e-3, 1.0, 1.0)
+    got = Dh[i, j]
+    X64d = torch.as_tensor(X64, device=dev)
+    T64d = torch.as_tensor(T64, device=dev)
+    D64 = tw.twed_batch(X64d, T64d, col.off, nu=1e-3, lam=1.0, p=1.0, precision="f64")
+    torch.cuda.synchronize()
+    D64h = D64.cpu().numpy()
+    off_diag = ~np.eye(n, dtype=bool)
+    rel = np.abs(Dh - D64h)[off_diag] / np.abs(D64h)[off_diag]
+    out = {"timed_output_vs_oracle": {"samples": samples, "max_rel_err": float(np.max(np.abs(got - ref) / ref))},
+           "fp64_gpu_vs_oracle_max_rel_err": float(np.max(np.abs(D64h[i, j] - ref) / ref)),
+           "fp32_vs_fp64_gpu_rel_err": {"max": float(rel.max()), "mean": float(rel.mean())}}
+    del D64, X64d, T64d
+    return out
+
+
+def paper_shapes(torch, tw, synth, dev):
+    """1-D FP64 workloads of the paper's tables: single pairs of random walks
+    N = 2^10 .. 2^20 (the C1 generator, seeds 0/1, t = 0..N-1, nu = 1e-3,
+    lambda = 1, L1) next to the paper's device-resident timings (table "Raw
+    Time to Solution", other hardware); all-pairs of 600 series of 60 and of
+    10 series of 1e5 (table "Timings From Validation Exercises" shapes, seeded
+    walks standing in for the UCI data)."""
+    out = {"single_pairs": {}}
+    f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+    big = synth.single_pair_1d(1 << 20)
+    for e in range(10, 21):
+        N = 1 << e
+        A, TA, B, TB = f64(big.A[:N]), f64(big.TA[:N]), f64(big.B[:N]), f64(big.TB[:N])
+        res = torch.empty(1, dtype=torch.float64, device=dev)
+        ws = torch.empty(max(tw.twed_pair_workspace_size(N, N, tw.make_params(1e-3, 1.0, 1.0, 1, "f64")), 256),
+                         dtype=torch.uint8, device=dev)
+        reps = 5 if N <= (1 << 16) else 2
+        _, per = time_steps(lambda: tw.twed_pair(A, TA, B, TB, 1e-3, 1.0, 1.0, "f64", out=res, workspace=ws),
+                            reps, 1, torch)
+        k = float(np.median(per))
+        out["single_pairs"][str(N)] = {"ms": round(k * 1e3, 4), "GCUPS": round(float(N) * N / k / 1e9, 3),
+                                       "paper_gpu_s": PAPER_CUTWED_DEV_S[N],
+                                       "speedup_vs_paper_gpu": round(PAPER_CUTWED_DEV_S[N] / k, 1)}
+    # (N = 2^20 also gives the 1-D FP64 roofline fraction)
+    k20 = out["single_pairs"][str(1 << 20)]["ms"] / 1e3
+    out["single_pairs_2^20_roofline_frac"] = round(OPS_PER_CELL_1D_L1_F64 * float(1 << 40) / k20 / 1e12
+                                                   / VALU_PEAK_TOPS, 4)
+    for count, length, paper_s, name in ((600, 60, 1.0, "600x60"), (10, 100_000, 147.0, "10x100k")):
+        col = synth.paper_shaped_collection(count, length)
+        X, T = f64(col.X), f64(col.T)
+        D = torch.empty((count, count), dtype=torch.float64, device=dev)
+        ws = torch.empty(max(tw.twed_batch_workspace_size(col.off, None, tw.make_params(1e-3, 1.0, 1.0, 1, "f64")),
+                             256), dtype=torch.uint8, device=dev)
+        _, per = time_steps(lambda: tw.twed_batch(X, T, col.off, nu=1e-3, lam=1.0, p=1.0, precision="f64", D=D,
+                                                  workspace=ws), 3, 1, torch)
+        k = float(np.median(per))
+        cells = float(length) * length * count * (count - 1) / 2
+        out[name] = {"ms": round(k * 1e3, 4), "GCUPS": round(cells / k / 1e9, 3),
+                     "paper_gpu_s": paper_s, "speedup_vs_paper_gpu": round(paper_s / k, 1),
+                     "note": "upper triangle swept; the paper's GPU run filled the full matrix"}
+    log(f"paper shapes: {out}")
+    return out
+
+
+def cpu_all_cores(pairs, synth):
+    """The oracle (FP64, one thread per pair) on a sample of the 2048-series
+    all-pairs batch, spread over every host core."""
+    import oracle
+    col = synth.batch_collection(2048, 64, 1024)
+    rng = np.random.default_rng(5)
+    i = rng.integers(0, 2048, pairs)
+    j = rng.integers(0, 2047, pairs)
+    j = j + (j >= i)
+    X64 = col.X.astype(np.float32).astype(np.float64)
+    T64 = col.T.astype(np.float32).astype(np.float64)
+    L = col.lengths
+    cells = float(np.sum(L[i].astype(np.float64) * L[j]))
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    oracle.get().pairs(X64, T64, col.off, X64, T64, col.off, np.stack([i, j], 1), 1e-3, 1.0, 1.0, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{pairs} random pairs of the 2048-series all-pairs batch ({cells:.3g} cells, {dt:.1f} s)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -218,6 +415,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    peaks = None
+    if not args.no_peaks:
+        peaks = measure_peaks(torch, dev)
+        log(f"peaks: {peaks}")
 
     # ---- headline: one 8-D pair, n = m = 1e6, FP32 costs + FP64 accumulators
     n = args.n
@@ -266,6 +468,36 @@ def main():
                      "ops_per_cell": OPS_PER_CELL_8D_L2_ACC64, "kernel_avg_s": kern_s},
     }
 
+    if peaks:
+        result["measured_peaks"] = peaks
+        # the sweep issues FP32 cost and FP64 accumulator operations; the
+        # lower of the two measured add+min rates is its ceiling
+        mp = min(peaks["f32_add_min_T_lane_op_s"], peaks["f64_add_min_T_lane_op_s"])
+        result["roofline"]["frac_of_measured_peak"] = round(achieved / mp, 4)
+
+    # ---- the same pair in FP64 on the GPU (inputs: the FP32 values widened),
+    # and the mixed-precision result's error against it
+    if not args.no_fp64:
+        f64 = lambda a: torch.as_tensor(np.ascontiguousarray(np.asarray(a, np.float32), dtype=np.float64), device=dev)
+        A64, TA64, B64, TB64 = f64(c.A), f64(c.TA), f64(c.B), f64(c.TB)
+        out64 = torch.empty(1, dtype=torch.float64, device=dev)
+        ws64 = torch.empty(max(tw.twed_pair_workspace_size(n, n, tw.make_params(c.nu, c.lam, c.p, 8, "f64")), 256),
+                           dtype=torch.uint8, device=dev)
+        w64, p64 = time_steps(lambda: tw.twed_pair(A64, TA64, B64, TB64, c.nu, c.lam, c.p, "f64", out=out64,
+                                                   workspace=ws64), 1, 0, torch)
+        v64 = float(out64.item())
+        result["headline_fp64"] = {
+            "workload": "the headline pair in FP64 (inputs, costs and accumulators; the FP32 inputs widened)",
+            "result": v64, "ms": round(p64[0] * 1e3, 3), "GCUPS": round(cells / p64[0] / 1e9, 3),
+            "mixed_vs_fp64_rel_err": abs(value - v64) / abs(v64)}
+        log(f"headline fp64: {result['headline_fp64']}")
+        del A64, TA64, B64, TB64, ws64
+
+    # ---- the 3-D pair n = m = 1e5 (irregular times, L2), FP64 and FP32,
+    # against the stored oracle values
+    if not args.no_c2:
+        result["pair_3d_n1e5"] = c2_bench(torch, tw, synth, dev, peaks)
+
     # ---- secondary: batched all-pairs, 2048 1-D FP32 series
     if not args.no_batch:
         log("generating batch collection 2048 x [64, 1024]")
@@ -291,7 +523,23 @@ def main():
             "GCUPS": round(bcells / bk / 1e9, 3),
             "roofline_frac": round(OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / VALU_PEAK_TOPS, 4),
         }
+        if peaks:
+            result["batched_all_pairs"]["frac_of_measured_peak"] = round(
+                OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / peaks["f32_add_min_T_lane_op_s"], 4)
+        result["batched_all_pairs"].update(batch_checks(torch, tw, col, X, T, D, dev))
+        # the same batch as a plan, before and after the autotuner
+        plan = tw.BatchPlan(col.off, precision="f32", device=dev)
+        _, dper = time_steps(lambda: plan.run(X, T, D=D), 3, 1, torch)
+        choice = plan.tune(X, T, D=D)
+        _, tper = time_steps(lambda: plan.run(X, T, D=D), 3, 1, torch)
+        plan.close()
+        result["batched_all_pairs"]["autotuned"] = {
+            "choice_chunk_waves_per_cu_lane_mode": list(choice),
+            "plan_default_ms": round(float(np.median(dper)) * 1e3, 3),
+            "plan_tuned_ms": round(float(np.median(tper)) * 1e3, 3),
+            "tuned_GCUPS": round(bcells / float(np.median(tper)) / 1e9, 3)}
         log(f"batch: {result['batched_all_pairs']}")
+        del D, bws
 
     # ---- one GPU's share of a column-sharded sweep, and the alignment path
     if not args.no_tiles:
@@ -405,6 +653,11 @@ def main():
             log(f"rn all-pairs: {result['rn_all_pairs']}")
             del aD, aws
 
+    # ---- the paper's own shapes (1-D FP64): single pairs N = 2^10 .. 2^20,
+    # 600 x 60 and 10 x 100k all-pairs
+    if not args.no_paper:
+        result["paper_shapes"] = paper_shapes(torch, tw, synth, dev)
+
     # ---- learned k-NN: train, index, query; recall against exhaustive TWED
     if args.knn:
         result["knn"] = knn_bench(args, torch, tw, synth, dev, time_steps)
@@ -422,6 +675,9 @@ def main():
                                   "kind": "oracle",
                                   "sample": f"{m}x{m} prefix of the headline pair (FP64 oracle, two-row "
                                             f"form, one thread; {dt:.1f} s)"}
+        if args.cpu_pairs > 0:
+            result["cpu_all_cores"] = cpu_all_cores(args.cpu_pairs, synth)
+            log(f"cpu all cores: {result['cpu_all_cores']}")
     print(json.dumps(result), flush=True)
     return 0
 

@@ -139,7 +139,7 @@ twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA,
                            const twed_params *prm, void *workspace, size_t ws_bytes,
                            hipStream_t stream, int32_t *strip_k, int32_t *group);
 
-/* Empties the tuning cache. */
+/* Empties the tuning cache (single-pair and batch choices). */
 void twed_tune_clear(void);
 
 /* ---- blocks of the DP matrix (section "Improved Time Warp Edit Distance":
@@ -264,9 +264,11 @@ twed_status twed_dp_path(int32_t kind, const void *A, int64_t nA, const void *B,
  * D: device, element type as `out` of twed_pair.  Every entry is
  * bitwise equal to what twed_pair returns for the same two series
  * and parameters, whichever operand is longer.
- * Errors as for twed_pair, plus TWED_ERR_INVALID for bad offsets and
- * TWED_ERR_UNSUPPORTED, in pair-list mode, when both collections hold a
- * series longer than twed_batch_max_short_length(dim). */
+ * Pairs whose shorter series is longer than twed_batch_max_short_length(dim)
+ * run the single-pair sweep one after another.  In pair-list mode, when both
+ * collections hold such series, the call reads the pair list back to the
+ * host to find them: it then synchronises `stream` before it returns.
+ * Errors as for twed_pair, plus TWED_ERR_INVALID for bad offsets. */
 size_t twed_batch_workspace_size(const int64_t *offX, int64_t nX,
                                  const int64_t *offY, int64_t nY,
                                  const twed_params *prm);
@@ -287,7 +289,10 @@ twed_status twed_batch(const void *X, const void *TX, const int64_t *offX, int64
  * nPairs results), nPairs == 0 the full matrix.
  * twed_batch_plan_run then enqueues kernels only on `stream` (staging, which
  * also clears the work ticket, the sweeps, the mirror and the widening), so
- * a caller can capture it in a HIP graph and replay it; X, TX, Y, TY, pairs
+ * a caller can capture it in a HIP graph and replay it (except a pair-list
+ * plan whose two collections both hold series longer than
+ * twed_batch_max_short_length(dim): its runs read the list back, see
+ * twed_batch); X, TX, Y, TY, pairs
  * and D as for twed_batch, with the planned shapes (Y, TY NULL exactly for a
  * symmetric plan, pairs given exactly for a pair-list plan; Y and TY may
  * also be NULL for a plan whose Y twed_batch_plan_stage_y staged).  Runs on one
@@ -315,9 +320,60 @@ twed_status twed_batch_plan_run(const twed_batch_plan *plan, const void *X, cons
 
 void twed_batch_plan_destroy(twed_batch_plan *plan);
 
+/* Batch autotuner (the paper plans light auto-tuning of its kernels, section
+ * "cuTWED Implementation Remarks").  A batch run is configured by: the
+ * consecutive items a wave takes per work ticket (chunk), the resident
+ * waves per compute unit, and, for a single query of at most 32 samples,
+ * whether each lane sweeps a whole pair (lane_mode 1) or each wave does
+ * (0).  By default rules choose them.  twed_batch_plan_tune runs the plan on
+ * the given inputs (as twed_batch_plan_run, several times: D is
+ * overwritten) under the rules' choice and then, one knob at a time, under
+ * each candidate (lane mode; chunk 1..64; a quarter, half or three quarters
+ * of the waves that fit), keeps the fastest (median of three runs) in the
+ * plan, and caches it under the plan's size class: device (architecture and
+ * compute units), precision, dimension, distance, mode (symmetric,
+ * rectangular, pair list), and the mean series lengths of X and Y and the
+ * number of pairs, each rounded down to a power of two.  Plans created
+ * afterwards, and twed_batch calls, of the same class use the cached choice.
+ * Synchronises `stream`.  Results never depend on the configuration: every
+ * entry is the same bits.  The chosen values go to *chunk, *waves_per_cu
+ * and *lane_mode when those are not NULL (0 / 0 / -1 mean the rule).
+ * Errors as twed_batch_plan_run. */
+twed_status twed_batch_plan_tune(twed_batch_plan *plan, const void *X, const void *TX,
+                                 const void *Y, const void *TY, const int64_t *pairs, void *D,
+                                 hipStream_t stream, int32_t *chunk, int32_t *waves_per_cu,
+                                 int32_t *lane_mode);
+
+/* The configuration a plan runs with (values as twed_batch_plan_tune's). */
+twed_status twed_batch_plan_config(const twed_batch_plan *plan, int32_t *chunk, int32_t *waves_per_cu,
+                                   int32_t *lane_mode);
+
+/* Writes the tuning cache (single-pair choices of twed_pair_tune and batch
+ * choices of twed_batch_plan_tune) to a text file, or merges such a file
+ * into it, so that measurements survive the process.  Entries carry the
+ * device they were measured on and apply only to that kind of device.
+ * Errors: TWED_ERR_INVALID for a NULL path, a file that cannot be opened or
+ * written, or (load) a malformed file, in which case nothing is merged. */
+twed_status twed_tune_save(const char *path);
+twed_status twed_tune_load(const char *path);
+
 /* Longest shorter-operand length a pair may have to be swept by a single
  * wave inside the batched kernel (longer pairs use the single-pair sweep). */
 int64_t twed_batch_max_short_length(int32_t dim);
+
+/* ---- measurement helper (not part of the distance computation) -------------
+ * Enqueues a loop of independent vector operations on `stream` so that the
+ * caller, timing it, measures the chip's vector lane-operation rate: the
+ * ceiling the sweeps' roofline fractions are taken against.  `waves` waves
+ * of 64 lanes (a multiple of 4, at most 2^24) each run `iters` iterations
+ * of eight independent chains of: kind 0 an FP32 fused multiply-add; 1 an
+ * FP32 add then minimum; 2 an FP64 fused multiply-add; 3 an FP64 add then
+ * minimum.  sink: device, waves*64 floats (kinds 0, 1) or doubles (2, 3),
+ * overwritten.  *lane_ops (host, may be NULL) receives the lane operations
+ * issued (an add and a minimum count as two).  Errors: TWED_ERR_INVALID for
+ * an unknown kind, iters < 1, a bad wave count or a NULL sink. */
+twed_status twed_probe_valu(int32_t kind, int64_t waves, int64_t iters, void *sink, double *lane_ops,
+                            hipStream_t stream);
 
 /* ---- status ---------------------------------------------------------------- */
 const char *twed_status_string(twed_status s);

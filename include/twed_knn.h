@@ -51,6 +51,17 @@ int64_t twed_embed_param_count(void);
 /* Longest series the network accepts (65,535 samples). */
 int64_t twed_embed_max_length(void);
 
+/* Memory bounds of the embedding forward pass and of twed_knn.  The forward
+ * pass over a collection embeds whole series, at most chunk_rows samples at
+ * a time (activation workspace about 0.3 KB per sample; a chunk always
+ * holds at least the longest series); twed_knn scores at most
+ * max(1, score_bytes / (4 nDB)) queries against the database at a time.
+ * 0 or a negative value restores the default (2^22 samples, 2^30 bytes).
+ * Process-wide; it changes the workspace sizes reported afterwards.  A call
+ * whose workspace was sized under a smaller limit than the one in force
+ * fails with TWED_ERR_WORKSPACE.  Results do not depend on the limits. */
+void twed_embed_set_limits(int64_t chunk_rows, int64_t score_bytes);
+
 /* Workspace bytes for twed_embed_forward (nPairs = 0) or
  * twed_embed_loss_grad (nPairs pairs) over the collection `off` (host,
  * nSeries+1 offsets).  0 if the offsets are invalid. */
@@ -121,8 +132,10 @@ size_t twed_knn_workspace_size(const twed_knn_index *index, const int64_t *offQ,
  * embedding distances (ties to lower ids); then exact FP32 TWED of every
  * (query, candidate) pair; ids[q*k + r] / dist[q*k + r] (device, int64 /
  * float) are the r-th smallest (distance, id).  With n_cand = nDB the
- * answer is the exact k-NN.  Needs every query or every database series
- * to be at most twed_batch_max_short_length(1) samples long.
+ * answer is the exact k-NN.  When queries and database both hold series
+ * longer than twed_batch_max_short_length(1), the candidate list is read
+ * back to the host to sweep those pairs one by one (see twed_batch), and
+ * the call synchronises `stream`.
  * Errors as twed_batch, plus TWED_ERR_INVALID for k or n_cand out of range
  * and an index that was not built. */
 twed_status twed_knn(const twed_knn_index *index, const void *Q, const void *TQ, const int64_t *offQ, int64_t nQ,

@@ -23,14 +23,16 @@ EXPORTS = [
     "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_matrix",
     "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
     "twed_batch_plan_create", "twed_batch_plan_run", "twed_batch_plan_destroy", "twed_batch_plan_stage_y",
+    "twed_batch_plan_tune", "twed_batch_plan_config", "twed_tune_save", "twed_tune_load",
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
     "twed_pair_tune", "twed_tune_clear",
     "twed_pair_tile_workspace_size", "twed_pair_tile", "twed_pair_path_workspace_size", "twed_pair_path",
     "twed_dp_workspace_size", "twed_dp", "twed_dp_path_workspace_size", "twed_dp_path",
-    "twed_embed_param_count", "twed_embed_max_length", "twed_embed_workspace_size", "twed_embed_forward",
+    "twed_embed_param_count", "twed_embed_max_length", "twed_embed_set_limits", "twed_embed_workspace_size",
+    "twed_embed_forward",
     "twed_embed_loss_grad", "twed_embed_adamw", "twed_knn_index_storage_size", "twed_knn_index_create",
     "twed_knn_index_build_workspace_size", "twed_knn_index_build", "twed_knn_workspace_size", "twed_knn",
-    "twed_knn_index_destroy",
+    "twed_knn_index_destroy", "twed_probe_valu",
 ]
 EMBED_DIM = 128
 
@@ -85,6 +87,15 @@ def load_library(path: str = LIB_PATH):
     L.twed_batch_plan_stage_y.restype = ctypes.c_int
     L.twed_batch_plan_destroy.argtypes = [_vp]
     L.twed_batch_plan_destroy.restype = None
+    _i32p = ctypes.POINTER(ctypes.c_int32)
+    L.twed_batch_plan_tune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32p, _i32p, _i32p]
+    L.twed_batch_plan_tune.restype = ctypes.c_int
+    L.twed_batch_plan_config.argtypes = [_vp, _i32p, _i32p, _i32p]
+    L.twed_batch_plan_config.restype = ctypes.c_int
+    L.twed_tune_save.argtypes = [ctypes.c_char_p]
+    L.twed_tune_save.restype = ctypes.c_int
+    L.twed_tune_load.argtypes = [ctypes.c_char_p]
+    L.twed_tune_load.restype = ctypes.c_int
     L.twed_pair_tune.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, ctypes.c_size_t, _vp,
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.twed_pair_tune.restype = ctypes.c_int
@@ -119,12 +130,16 @@ def load_library(path: str = LIB_PATH):
     L.twed_stream_check.restype = ctypes.c_int
     L.twed_version.argtypes = []
     L.twed_version.restype = ctypes.c_char_p
+    L.twed_probe_valu.argtypes = [ctypes.c_int32, _i64, _i64, _vp, ctypes.POINTER(ctypes.c_double), _vp]
+    L.twed_probe_valu.restype = ctypes.c_int
     # embedding network and k-NN index (include/twed_knn.h)
     _sz = ctypes.c_size_t
     L.twed_embed_param_count.argtypes = []
     L.twed_embed_param_count.restype = _i64
     L.twed_embed_max_length.argtypes = []
     L.twed_embed_max_length.restype = _i64
+    L.twed_embed_set_limits.argtypes = [_i64, _i64]
+    L.twed_embed_set_limits.restype = None
     L.twed_embed_workspace_size.argtypes = [_i64p, _i64, _i64]
     L.twed_embed_workspace_size.restype = _sz
     L.twed_embed_forward.argtypes = [_vp, _vp, _i64p, _i64, _vp, _vp, _sz, _vp]
@@ -531,6 +546,41 @@ class BatchPlan:
                                                   D.data_ptr(), _stream(stream)))
         return D
 
+    def _args(self, X, TX, Y, TY, pairs):
+        torch = _torch()
+        dt = input_dtype(self.precision)
+        X2 = X if X.dim() == 2 else X.reshape(-1, 1)
+        _dev(X2, dt, "X"); _dev(TX, dt, "TX")
+        if X2.shape[1] != self.dim:
+            raise ValueError("X has a different dimension than the plan")
+        Yp = TYp = None
+        if Y is not None:
+            Y2 = Y if Y.dim() == 2 else Y.reshape(-1, 1)
+            _dev(Y2, dt, "Y"); _dev(TY, dt, "TY")
+            Yp, TYp = Y2.data_ptr(), TY.data_ptr()
+        pp = None
+        if pairs is not None:
+            _dev(pairs, torch.int64, "pairs")
+            pp = pairs.data_ptr()
+        return X2.data_ptr(), TX.data_ptr(), Yp, TYp, pp
+
+    def tune(self, X, TX, Y=None, TY=None, pairs=None, D=None, stream=None):
+        """Measures the batch configurations on these inputs (twed_batch_plan_tune);
+        returns the chosen (chunk, waves_per_cu, lane_mode)."""
+        if D is None:
+            D = self.output()
+        c, w, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().twed_batch_plan_tune(self._h, *self._args(X, TX, Y, TY, pairs), D.data_ptr(),
+                                                   _stream(stream), ctypes.byref(c), ctypes.byref(w),
+                                                   ctypes.byref(l)))
+        return c.value, w.value, l.value
+
+    def config(self):
+        """(chunk, waves_per_cu, lane_mode) this plan runs with (0 / 0 / -1: the rules)."""
+        c, w, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().twed_batch_plan_config(self._h, ctypes.byref(c), ctypes.byref(w), ctypes.byref(l)))
+        return c.value, w.value, l.value
+
     def close(self):
         if self._h is not None:
             load_library().twed_batch_plan_destroy(self._h)
@@ -541,6 +591,16 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def twed_tune_save(path) -> None:
+    """Writes the tuning cache (single-pair and batch choices) to a file."""
+    _check(load_library().twed_tune_save(os.fsencode(path)))
+
+
+def twed_tune_load(path) -> None:
+    """Merges a tuning cache file written by twed_tune_save."""
+    _check(load_library().twed_tune_load(os.fsencode(path)))
 
 
 def twed_stream_check(stream=None):
@@ -572,6 +632,12 @@ def twed_embed_param_count() -> int:
 
 def twed_embed_max_length() -> int:
     return int(load_library().twed_embed_max_length())
+
+
+def twed_embed_set_limits(chunk_rows: int = 0, score_bytes: int = 0) -> None:
+    """Forward-pass chunk (samples) and k-NN score-chunk (bytes) limits;
+    0 restores the defaults (twed_embed_set_limits in twed_knn.h)."""
+    load_library().twed_embed_set_limits(int(chunk_rows), int(score_bytes))
 
 
 def twed_embed_forward(params, X, off, emb=None, workspace=None, stream=None):

@@ -1,6 +1,6 @@
 """Builds libtwed.so (HIP, gfx950) in-tree.
 
-    python -m paper_2007_16135_amd.build [--jobs N]
+    python -m paper_2007_16135_amd.build [--jobs N] [--incremental]
 
 Each source in csrc/ is compiled to an object under _build/ in parallel, then
 linked into paper_2007_16135_amd/libtwed.so.
@@ -11,6 +11,7 @@ import argparse
 import concurrent.futures as cf
 import glob
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -42,12 +43,39 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
-def build(jobs: int | None = None, extra=()) -> str:
+_INCLUDE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def _deps(path: str, seen: set) -> set:
+    """path and every file it includes with #include "..." (recursively)."""
+    path = os.path.normpath(path)
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        for inc in _INCLUDE.findall(f.read()):
+            _deps(os.path.join(os.path.dirname(path), inc), seen)
+    return seen
+
+
+def _stale(src: str) -> bool:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps(src, set()))
+
+
+def build(jobs: int | None = None, extra=(), incremental: bool = False) -> str:
+    """Compiles every source (or, with incremental, those whose object is
+    older than the source or than a file it includes) and links libtwed.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2)))
+    todo = [s for s in srcs if _stale(s)] if incremental else srcs
+    jobs = jobs or min(max(1, len(todo)), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, list(extra)), srcs))
+        list(ex.map(lambda s: _compile(s, list(extra)), todo))
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,8 +88,10 @@ def build(jobs: int | None = None, extra=()) -> str:
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only sources older than their object or the headers")
     a = ap.parse_args(argv)
-    print(build(a.jobs))
+    print(build(a.jobs, incremental=a.incremental))
 
 
 if __name__ == "__main__":

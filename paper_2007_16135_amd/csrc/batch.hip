@@ -144,10 +144,12 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
                 a = pairs[2 * item];
                 b = pairs[2 * item + 1];
             }
-            // a pair-list entry outside the collections yields NaN (swept as (0, 0))
+            // a pair-list entry outside the collections yields NaN
             const bool ok = a >= 0 && a < nX && b >= 0 && b < nY;
-            a = ok ? a : 0;
-            b = ok ? b : 0;
+            if (!ok) {  // uniform: one item per wave
+                D[item] = (AT)__builtin_nan("");
+                continue;
+            }
             const int64_t xa = offX[a], la = offX[a + 1] - xa;
             const int64_t yb = offY[b], lb = offY[b + 1] - yb;
             const CT *ra = rowsX + (xa + a) * S;
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
                     D[a * nX + b] = d;
                     D[b * nX + a] = d;
                 } else {
-                    D[item] = ok ? d : (AT)__builtin_nan("");
+                    D[item] = d;
                 }
             }
         }

@@ -71,6 +71,20 @@ inline void *take_rows(Carver &c, Prec prec, int dimt, int64_t rows)
     return p ? p + (size_t)kRowPad * (size_t)row_stride(prec, dimt) * cost_size(prec) : nullptr;
 }
 
+// Device bytes of the single-pair sweep state (boundary slots, then flags
+// and tail words) for series of up to maxlen samples (twed_capi.hip).
+size_t long_pair_state_bytes(Prec prec, int64_t maxlen);
+
+// Pairs of a device pair list whose shorter series is too long for the
+// batched kernel's single wave: reads the list back (synchronising `st`) and
+// runs the single-pair sweep of each such pair into D[k] (accumulator type).
+// rowsX / rowsY: staged rows; offX / offY: host offsets of nX / nY series;
+// state: long_pair_state_bytes(prec, maxlen) bytes (twed_capi.hip).
+twed_status sweep_long_listed_pairs(Prec prec, const CostParams &cp, const twed_params *prm, const void *rowsX,
+                                    const int64_t *offX, int64_t nX, const void *rowsY, const int64_t *offY,
+                                    int64_t nY, const int64_t *pairs, int64_t nPairs, void *state,
+                                    int64_t maxlen, void *D, hipStream_t st);
+
 inline bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
 inline twed_status check_params(const twed_params *prm)

@@ -10,6 +10,7 @@
 #include "twed_kernels.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -35,10 +36,13 @@ struct twed_knn_index {
 
 namespace {
 
-// Rows of one forward chunk for large collections (whole series per chunk).
-constexpr int64_t kMaxChunkRows = int64_t(1) << 22;
-// Score matrix bytes per query chunk of a k-NN call.
-constexpr int64_t kScoreBytes = int64_t(1) << 30;
+// Default rows of one forward chunk for large collections (whole series per
+// chunk) and score-matrix bytes per query chunk of a k-NN call; both can be
+// lowered (or raised) with twed_embed_set_limits.
+constexpr int64_t kDefaultChunkRows = int64_t(1) << 22;
+constexpr int64_t kDefaultScoreBytes = int64_t(1) << 30;
+std::atomic<int64_t> g_chunk_rows{kDefaultChunkRows};
+std::atomic<int64_t> g_score_bytes{kDefaultScoreBytes};
 
 struct Weights {
     uint16_t *wt[kLayers], *wb[kLayers];
@@ -122,7 +126,13 @@ hipError_t forward(const float *params, const Weights &w, const Acts &a, const f
     return launch_pool(a.y4, off, nS, row_base, R, emb, emb16, sqnorm, st);
 }
 
-int64_t chunk_rows_for(int64_t total) { return std::min(total, kMaxChunkRows); }
+// Rows of the activation buffers: the whole collection if it fits the
+// chunk limit, else the limit, but never less than the longest series (a
+// series is never split across chunks).
+int64_t chunk_rows_for(int64_t total, int64_t maxlen)
+{
+    return std::min(total, std::max(g_chunk_rows.load(std::memory_order_relaxed), maxlen));
+}
 
 // Chunked forward over a whole collection (host offsets offH, device offD).
 hipError_t forward_all(const float *params, const Weights &w, const Acts &a, const float *X, const int64_t *offH,
@@ -165,14 +175,14 @@ struct EmbedLayout {
     size_t total;
 };
 
-EmbedLayout embed_layout(char *base, int64_t n, int64_t total, int64_t nPairs)
+EmbedLayout embed_layout(char *base, int64_t n, int64_t total, int64_t maxlen, int64_t nPairs)
 {
     Carver c{base};
     EmbedLayout L{};
     L.off = (int64_t *)c.take((size_t)(n + 1) * 8);
     take_weights(c, L.w);
     const bool train = nPairs > 0;
-    take_acts(c, L.a, train ? total : chunk_rows_for(total), train);
+    take_acts(c, L.a, train ? total : chunk_rows_for(total, maxlen), train);
     if (train) {
         L.emb = (float *)c.take((size_t)n * kEmb * 4);
         L.demb = (float *)c.take((size_t)n * kEmb * 4);
@@ -236,19 +246,20 @@ struct BuildLayout {
     size_t total;
 };
 
-BuildLayout build_layout(char *base, int64_t total)
+BuildLayout build_layout(char *base, int64_t total, int64_t maxlen)
 {
     Carver c{base};
     BuildLayout L{};
     take_weights(c, L.w);
-    take_acts(c, L.a, chunk_rows_for(total), false);
+    take_acts(c, L.a, chunk_rows_for(total, maxlen), false);
     L.total = c.used;
     return L;
 }
 
 int64_t queries_per_chunk(int64_t nQ, int64_t nDB)
 {
-    return std::max<int64_t>(1, std::min<int64_t>(nQ, kScoreBytes / (nDB * 4)));
+    const int64_t bytes = g_score_bytes.load(std::memory_order_relaxed);
+    return std::max<int64_t>(1, std::min<int64_t>(nQ, bytes / (nDB * 4)));
 }
 
 struct KnnLayout {
@@ -261,10 +272,12 @@ struct KnnLayout {
     float *sqnorm, *scores, *dist;
     int32_t *cand;
     int64_t *pairs;
+    void *long_state;  // single-pair sweep state, when queries and database both hold long series
     size_t total;
 };
 
-KnnLayout knn_layout(char *base, int64_t nQ, int64_t totQ, int64_t nDB, int64_t n_cand)
+KnnLayout knn_layout(char *base, int64_t nQ, int64_t totQ, int64_t maxQ, int64_t nDB, int64_t maxDB,
+                     int64_t n_cand)
 {
     Carver c{base};
     KnnLayout L{};
@@ -272,13 +285,16 @@ KnnLayout knn_layout(char *base, int64_t nQ, int64_t totQ, int64_t nDB, int64_t 
     L.rowsQ = take_rows(c, kF32, dimt_for(1), totQ + nQ);
     L.ticket = (uint32_t *)c.take(4);
     take_weights(c, L.w);
-    take_acts(c, L.a, chunk_rows_for(totQ), false);
+    take_acts(c, L.a, chunk_rows_for(totQ, maxQ), false);
     L.emb16 = (uint16_t *)c.take((size_t)nQ * kEmb * 2);
     L.sqnorm = (float *)c.take((size_t)nQ * 4);
     L.scores = (float *)c.take((size_t)queries_per_chunk(nQ, nDB) * nDB * 4);
     L.cand = (int32_t *)c.take((size_t)nQ * n_cand * 4);
     L.pairs = (int64_t *)c.take((size_t)nQ * n_cand * 16);
     L.dist = (float *)c.take((size_t)nQ * n_cand * 4);
+    L.long_state = std::min(maxQ, maxDB) > twed_batch_max_short_length(1)
+                       ? c.take(long_pair_state_bytes(kF32, std::max(maxQ, maxDB)))
+                       : nullptr;
     L.total = c.used;
     return L;
 }
@@ -291,11 +307,17 @@ int64_t twed_embed_param_count(void) { return kParamCount; }
 
 int64_t twed_embed_max_length(void) { return kMaxSeriesLen; }
 
+void twed_embed_set_limits(int64_t chunk_rows, int64_t score_bytes)
+{
+    g_chunk_rows.store(chunk_rows > 0 ? chunk_rows : kDefaultChunkRows, std::memory_order_relaxed);
+    g_score_bytes.store(score_bytes > 0 ? score_bytes : kDefaultScoreBytes, std::memory_order_relaxed);
+}
+
 size_t twed_embed_workspace_size(const int64_t *off, int64_t nSeries, int64_t nPairs)
 {
     int64_t maxlen, total;
     if (nPairs < 0 || check_network_offsets(off, nSeries, &maxlen, &total) != TWED_OK) return 0;
-    return embed_layout(nullptr, nSeries, total, nPairs).total;
+    return embed_layout(nullptr, nSeries, total, maxlen, nPairs).total;
 }
 
 twed_status twed_embed_forward(const float *params, const float *X, const int64_t *off, int64_t nSeries, float *emb,
@@ -306,14 +328,15 @@ twed_status twed_embed_forward(const float *params, const float *X, const int64_
     int64_t maxlen, total;
     twed_status s = check_network_offsets(off, nSeries, &maxlen, &total);
     if (s != TWED_OK) return s;
-    s = check_workspace(workspace, ws_bytes, embed_layout(nullptr, nSeries, total, 0).total);
+    s = check_workspace(workspace, ws_bytes, embed_layout(nullptr, nSeries, total, maxlen, 0).total);
     if (s != TWED_OK) return s;
-    const EmbedLayout L = embed_layout((char *)workspace, nSeries, total, 0);
+    const EmbedLayout L = embed_layout((char *)workspace, nSeries, total, maxlen, 0);
     hipError_t e = hipMemcpyAsync(L.off, off, (size_t)(nSeries + 1) * 8, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail_hip(e, "offset upload");
     e = make_weights(params, L.w, st);
     if (e != hipSuccess) return fail_hip(e, "weight copies");
-    e = forward_all(params, L.w, L.a, X, off, L.off, nSeries, chunk_rows_for(total), emb, nullptr, nullptr, st);
+    e = forward_all(params, L.w, L.a, X, off, L.off, nSeries, chunk_rows_for(total, maxlen), emb, nullptr, nullptr,
+                    st);
     if (e != hipSuccess) return fail_hip(e, "forward launch");
     return TWED_OK;
 }
@@ -330,9 +353,9 @@ twed_status twed_embed_loss_grad(const float *params, const float *X, const int6
     twed_status s = check_network_offsets(off, nSeries, &maxlen, &total);
     if (s != TWED_OK) return s;
     if (total > 0x7fffffffLL) return fail(TWED_ERR_UNSUPPORTED, "more than 2^31 - 1 samples in one training batch");
-    s = check_workspace(workspace, ws_bytes, embed_layout(nullptr, nSeries, total, nPairs).total);
+    s = check_workspace(workspace, ws_bytes, embed_layout(nullptr, nSeries, total, maxlen, nPairs).total);
     if (s != TWED_OK) return s;
-    const EmbedLayout L = embed_layout((char *)workspace, nSeries, total, nPairs);
+    const EmbedLayout L = embed_layout((char *)workspace, nSeries, total, maxlen, nPairs);
     const Acts &a = L.a;
     const int64_t R = total;
     float *E = emb ? emb : L.emb;
@@ -464,16 +487,16 @@ twed_status twed_knn_index_create(const void *DB, const void *TDB, const int64_t
 size_t twed_knn_index_build_workspace_size(const twed_knn_index *ix)
 {
     if (!ix) return 0;
-    return build_layout(nullptr, ix->total).total;
+    return build_layout(nullptr, ix->total, ix->maxlen).total;
 }
 
 twed_status twed_knn_index_build(twed_knn_index *ix, void *workspace, size_t ws_bytes, hipStream_t st)
 {
     last_error().clear();
     if (!ix) return fail(TWED_ERR_INVALID, "index is NULL");
-    twed_status s = check_workspace(workspace, ws_bytes, build_layout(nullptr, ix->total).total);
+    twed_status s = check_workspace(workspace, ws_bytes, build_layout(nullptr, ix->total, ix->maxlen).total);
     if (s != TWED_OK) return s;
-    const BuildLayout L = build_layout((char *)workspace, ix->total);
+    const BuildLayout L = build_layout((char *)workspace, ix->total, ix->maxlen);
     hipError_t e = hipMemcpyAsync(ix->off_dev, ix->off.data(), (size_t)(ix->nDB + 1) * 8, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail_hip(e, "offset upload");
     const CostParams cp = cost_params(&ix->prm);
@@ -482,8 +505,8 @@ twed_status twed_knn_index_build(twed_knn_index *ix, void *workspace, size_t ws_
     if (e != hipSuccess) return fail_hip(e, "staging launch");
     e = make_weights(ix->params, L.w, st);
     if (e != hipSuccess) return fail_hip(e, "weight copies");
-    e = forward_all(ix->params, L.w, L.a, ix->DB, ix->off.data(), ix->off_dev, ix->nDB, chunk_rows_for(ix->total),
-                    nullptr, ix->emb16, ix->sqnorm, st);
+    e = forward_all(ix->params, L.w, L.a, ix->DB, ix->off.data(), ix->off_dev, ix->nDB,
+                    chunk_rows_for(ix->total, ix->maxlen), nullptr, ix->emb16, ix->sqnorm, st);
     if (e != hipSuccess) return fail_hip(e, "forward launch");
     ix->built = true;
     return TWED_OK;
@@ -494,7 +517,7 @@ size_t twed_knn_workspace_size(const twed_knn_index *ix, const int64_t *offQ, in
     int64_t maxlen, total;
     if (!ix || k < 1 || n_cand < k || n_cand > ix->nDB) return 0;
     if (check_network_offsets(offQ, nQ, &maxlen, &total) != TWED_OK) return 0;
-    return knn_layout(nullptr, nQ, total, ix->nDB, n_cand).total;
+    return knn_layout(nullptr, nQ, total, maxlen, ix->nDB, ix->maxlen, n_cand).total;
 }
 
 twed_status twed_knn(const twed_knn_index *ix, const void *Q, const void *TQ, const int64_t *offQ, int64_t nQ,
@@ -509,15 +532,11 @@ twed_status twed_knn(const twed_knn_index *ix, const void *Q, const void *TQ, co
     int64_t maxQ, totQ;
     twed_status s = check_network_offsets(offQ, nQ, &maxQ, &totQ);
     if (s != TWED_OK) return s;
-    const int64_t kshort = twed_batch_max_short_length(1);
-    if (std::min(maxQ, ix->maxlen) > kshort)
-        return fail(TWED_ERR_UNSUPPORTED, "queries or database series must be at most "
-                                          "twed_batch_max_short_length(1) samples long");
     const int64_t nItems = nQ * (int64_t)n_cand;
     if (nItems > 0xffffffffLL) return fail(TWED_ERR_UNSUPPORTED, "more than 2^32 - 1 query-candidate pairs");
-    s = check_workspace(workspace, ws_bytes, knn_layout(nullptr, nQ, totQ, ix->nDB, n_cand).total);
+    s = check_workspace(workspace, ws_bytes, knn_layout(nullptr, nQ, totQ, maxQ, ix->nDB, ix->maxlen, n_cand).total);
     if (s != TWED_OK) return s;
-    const KnnLayout L = knn_layout((char *)workspace, nQ, totQ, ix->nDB, n_cand);
+    const KnnLayout L = knn_layout((char *)workspace, nQ, totQ, maxQ, ix->nDB, ix->maxlen, n_cand);
     const CostParams cp = cost_params(&ix->prm);
     hipError_t e;
 #define TRY(call, what)                                \
@@ -529,7 +548,7 @@ twed_status twed_knn(const twed_knn_index *ix, const void *Q, const void *TQ, co
     // queries staged for the sweep (zeroing the batch ticket), then embedded
     TRY(launch_stage(kF32, cp, Q, TQ, L.offQ, nQ, 0, maxQ, totQ + nQ, L.rowsQ, L.ticket, 1, st), "staging");
     TRY(make_weights(ix->params, L.w, st), "weight copies");
-    TRY(forward_all(ix->params, L.w, L.a, (const float *)Q, offQ, L.offQ, nQ, chunk_rows_for(totQ), nullptr,
+    TRY(forward_all(ix->params, L.w, L.a, (const float *)Q, offQ, L.offQ, nQ, chunk_rows_for(totQ, maxQ), nullptr,
                     L.emb16, L.sqnorm, st),
         "forward");
     // squared embedding distances and the n_cand smallest per query
@@ -574,6 +593,12 @@ twed_status twed_knn(const twed_knn_index *ix, const void *Q, const void *TQ, co
     if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
     b.grid = (int)std::min<int64_t>(nItems, workers);
     TRY(launch_batch(kF32, cp, b, st), "re-rank launch");
+    if (L.long_state) {
+        // pairs of two series longer than one wave's strip: single-pair sweeps
+        s = sweep_long_listed_pairs(kF32, cp, &ix->prm, L.rowsQ, offQ, nQ, ix->rows, ix->off.data(), ix->nDB,
+                                    L.pairs, nItems, L.long_state, std::max(maxQ, ix->maxlen), L.dist, st);
+        if (s != TWED_OK) return s;
+    }
     TRY(launch_final_topk(L.dist, L.cand, (int)nQ, n_cand, k, ids, dist, st), "final selection");
 #undef TRY
     return TWED_OK;

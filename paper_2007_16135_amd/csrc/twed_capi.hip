@@ -79,10 +79,6 @@ int choose_k(const twed_params *prm, int64_t nB, Prec prec, const CostParams &cp
     return 1;
 }
 
-// Single pairs take the wavefront sweep unless the caller asks for the
-// per-diagonal one.
-bool wavefront_enabled() { return true; }
-
 // Words after the per-strip flags in the zeroed region: work ticket, wait
 // timeout flag, and two words holding the FP32 cost offset.
 constexpr int64_t kTailWords = 4;
@@ -103,7 +99,7 @@ PairLayout pair_layout(char *base, int64_t nA, int64_t nB, const twed_params *pr
     PairLayout L{};
     L.rowsA = take_rows(c, prec, dimt, nA + 1);
     L.rowsB = take_rows(c, prec, dimt, nB + 1);
-    if (prm->algo == TWED_ALGO_DIAGONAL || (prm->algo == TWED_ALGO_AUTO && !wavefront_enabled())) {
+    if (prm->algo == TWED_ALGO_DIAGONAL) {
         for (int i = 0; i < 3; ++i) L.z[i] = c.take((size_t)(nB + 1) * as);
         for (int i = 0; i < 3; ++i) L.x[i] = c.take((size_t)(nB + 1) * as);
         L.bnd = nullptr;
@@ -132,7 +128,20 @@ struct SweepChoice {
     int K, G, sub_shift;
 };
 
-using TuneKey = std::tuple<int, int, int, int64_t>;
+// Identity of the current device in the tuning caches (architecture name and
+// compute-unit count), so that a saved cache serves only the same hardware.
+std::string device_id()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + "-cu" + std::to_string(prop.multiProcessorCount);
+}
+
+using TuneKey = std::tuple<std::string, int, int, int, int64_t>;
 
 std::mutex &tune_mutex()
 {
@@ -149,7 +158,7 @@ std::map<TuneKey, SweepChoice> &tune_cache()
 bool tuned_choice(Prec prec, const CostParams &cp, int64_t nB, SweepChoice *out)
 {
     std::lock_guard<std::mutex> lock(tune_mutex());
-    const auto it = tune_cache().find(TuneKey{(int)prec, cp.dimt, cp.pm, nB});
+    const auto it = tune_cache().find(TuneKey{device_id(), (int)prec, cp.dimt, cp.pm, nB});
     if (it == tune_cache().end()) return false;
     *out = it->second;
     return true;
@@ -168,7 +177,7 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
         e = launch_offset(prec, cp, rowsA, nA, rowsB, nB, beta, st);
         if (e != hipSuccess) return fail_hip(e, "offset launch");
     }
-    if (prm->algo == TWED_ALGO_DIAGONAL || (prm->algo == TWED_ALGO_AUTO && !wavefront_enabled())) {
+    if (prm->algo == TWED_ALGO_DIAGONAL) {
         if (!diag_layout) return fail(TWED_ERR_UNSUPPORTED, "no single-pair sweep available for this call");
         DiagonalArgs d{};
         d.rowsA = rowsA;
@@ -186,9 +195,6 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
         if (e != hipSuccess) return fail_hip(e, "diagonal sweep launch");
         return TWED_OK;
     }
-    if (!wavefront_enabled())
-        return fail(TWED_ERR_UNSUPPORTED, "the wavefront sweep is switched off in this build "
-                                          "(an unexplained stall on its first device run is under investigation)");
     SweepChoice tuned{};
     const bool have_tuned = !force && !dump && prm->strip_k == 0 && tuned_choice(prec, cp, nB, &tuned);
     int K = force ? force->K : (have_tuned ? tuned.K : choose_k(prm, nB, prec, cp));
@@ -328,6 +334,30 @@ BatchLayout batch_layout(char *base, int64_t totX, int64_t nX, int64_t maxX, int
 // twed_batch = prepare + upload + enqueue in one call.  A twed_batch_plan
 // keeps the prepared state so that later runs enqueue kernels only (and can
 // therefore be captured in a HIP graph).
+// A batch run is configured by the number of consecutive items a wave takes
+// per work ticket, the resident waves per compute unit, and whether a single
+// short query runs one lane per pair.  The defaults come from rules;
+// twed_batch_plan_tune measures the candidates on a plan's own inputs and
+// caches the fastest under the plan's size class, which later plans and
+// twed_batch calls of that class use.
+struct BatchConfig {
+    int chunk = 0;         // items per ticket (0: rule)
+    int waves_per_cu = 0;  // resident waves per compute unit (0: all that fit)
+    int lane_mode = -1;    // single short query: 1 lane per pair (1), wave per pair (0), rule (-1)
+};
+
+// Size class: device, precision, compiled dimension, distance, mode, and the
+// mean lengths of X and Y and the item count rounded down to powers of two.
+using BatchKey = std::tuple<std::string, int, int, int, int, int, int, int>;
+
+std::map<BatchKey, BatchConfig> &batch_cache()
+{
+    static std::map<BatchKey, BatchConfig> c;
+    return c;
+}
+
+int floor_log2(double v) { return v < 2.0 ? 0 : (int)std::floor(std::log2(v)); }
+
 struct BatchPlan {
     twed_params prm;
     Prec prec;
@@ -338,7 +368,25 @@ struct BatchPlan {
     int64_t nX, nY, maxX, maxY, totX, totY, nPairs;
     bool sym, list;
     bool y_staged = false;  // rows of Y staged by twed_batch_plan_stage_y
+    BatchKey key;
+    BatchConfig cfg;
 };
+
+int64_t batch_items(const BatchPlan &P)
+{
+    return P.list ? P.nPairs : (P.sym ? P.nX * (P.nX - 1) / 2 : P.nX * P.nY);
+}
+
+BatchKey batch_key(const BatchPlan &P)
+{
+    const int mode = P.list ? kPairList : (P.sym ? kSymmetric : kRect);
+    return BatchKey{device_id(), (int)P.prec, P.cp.dimt, P.cp.pm, mode,
+                    floor_log2((double)P.totX / (double)P.nX), floor_log2((double)P.totY / (double)P.nY),
+                    floor_log2((double)std::max<int64_t>(1, batch_items(P)))};
+}
+
+// A single query short enough for one lane per pair (rectangular mode).
+bool lane_eligible(const BatchPlan &P) { return !P.sym && !P.list && P.nX == 1 && P.maxX <= kLaneMaxQuery; }
 
 twed_status batch_prepare(const int64_t *offX, int64_t nX, const int64_t *offY, int64_t nY, bool sym, bool list,
                           int64_t nPairs, const twed_params *prm, void *workspace, size_t ws_bytes, BatchPlan &P)
@@ -359,10 +407,6 @@ twed_status batch_prepare(const int64_t *offX, int64_t nX, const int64_t *offY, 
     }
     if (list && nPairs < 0) return fail(TWED_ERR_INVALID, "nPairs must be >= 0");
     if (nX * nY > (int64_t(1) << 40)) return fail(TWED_ERR_UNSUPPORTED, "too many pairs");
-    const int64_t kshort = twed_batch_max_short_length(prm->dim);
-    if (list && std::min(maxX, maxY) > kshort)
-        return fail(TWED_ERR_UNSUPPORTED, "pair lists need one collection of series no longer than "
-                                          "twed_batch_max_short_length(dim)");
     const Prec prec = resolve(prm, std::max(maxX, maxY));
     const BatchLayout need = batch_layout(nullptr, totX, nX, maxX, totY, nY, maxY, sym, nX * nY, prm, prec);
     s = check_workspace(workspace, ws_bytes, need.total);
@@ -390,6 +434,13 @@ twed_status batch_prepare(const int64_t *offX, int64_t nX, const int64_t *offY, 
     P.nPairs = list ? nPairs : 0;
     P.sym = sym;
     P.list = list;
+    P.key = batch_key(P);
+    P.cfg = BatchConfig{};
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        const auto it = batch_cache().find(P.key);
+        if (it != batch_cache().end()) P.cfg = it->second;
+    }
     return TWED_OK;
 }
 
@@ -461,29 +512,44 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
     b.D = Dk;
     b.ticket = (uint32_t *)L.zero;
     if (b.nItems > 0xffffffffLL) return fail(TWED_ERR_UNSUPPORTED, "more than 2^32 - 1 pairs in one call");
-    const int workers = batch_max_workers(prec, cp);
+    int workers = batch_max_workers(prec, cp);
     if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+    if (P.cfg.waves_per_cu > 0) {
+        const int cus = std::max(1, device_simds() / 4);
+        workers = std::min(workers, P.cfg.waves_per_cu * cus);
+    }
     if (sym) {
         e = launch_batch_diag_zero(prec, Dk, nX, st);
         if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
     }
-    if (b.nItems > 0 && !pairs && !sym && nX == 1 && maxX <= kLaneMaxQuery) {
+    const bool lane = lane_eligible(P) && P.cfg.lane_mode != 0;
+    if (b.nItems > 0 && lane) {
         // one short query: a lane per pair
         e = launch_batch_lane(prec, cp, L.rowsX, (int)maxX, L.rowsY, (const int64_t *)L.offY, nY, Dk,
                               (uint32_t *)L.zero, (int)std::min<int64_t>((nY + 63) / 64, workers), st);
         if (e != hipSuccess) return fail_hip(e, "batch launch");
     } else if (b.nItems > 0) {
-        // items per ticket: about 64k cells of work per ticket for short
-        // pairs, while leaving at least four tickets per wave
-        const double cells = (double)totX / (double)nX * (double)totY / (double)nY;
-        int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(65536.0 / std::max(cells, 1.0))));
-        chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, b.nItems / (4 * (int64_t)workers)));
+        int64_t chunk = P.cfg.chunk;
+        if (chunk <= 0) {
+            // items per ticket: about 64k cells of work per ticket for short
+            // pairs, while leaving at least four tickets per wave
+            const double cells = (double)totX / (double)nX * (double)totY / (double)nY;
+            chunk = std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(65536.0 / std::max(cells, 1.0))));
+            chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, b.nItems / (4 * (int64_t)workers)));
+        }
         b.chunk = (int)chunk;
         b.grid = (int)std::min<int64_t>((b.nItems + chunk - 1) / chunk, workers);
         e = launch_batch(prec, cp, b, st);
         if (e != hipSuccess) return fail_hip(e, "batch launch");
     }
 
+    // listed pairs whose shorter series exceeds one wave (the batch kernel
+    // leaves them): the list is read back and each runs the single-pair sweep
+    if (pairs && std::min(maxX, maxY) > kshort) {
+        s = sweep_long_listed_pairs(prec, cp, prm, L.rowsX, offX, nX, L.rowsY, sym ? offX : offY, nY, pairs, nPairs,
+                                    L.bnd, std::max(maxX, maxY), Dk, st);
+        if (s != TWED_OK) return s;
+    }
     // pairs whose shorter series exceeds one wave: single-pair sweeps
     if (!pairs && std::min(maxX, maxY) > kshort) {
         const size_t S = (size_t)row_stride(prec, cp.dimt), cs = cost_size(prec), as = acc_size(prec);
@@ -525,6 +591,52 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
 }
 
 }  // namespace
+
+namespace twed {
+namespace capi {
+
+size_t long_pair_state_bytes(Prec prec, int64_t maxlen)
+{
+    const size_t as = acc_size(prec);
+    return align_up((size_t)2 * (size_t)(maxlen + 1) * 2 * as) +
+           align_up((size_t)((maxlen + 63) / 64 + kTailWords) * 4);
+}
+
+twed_status sweep_long_listed_pairs(Prec prec, const CostParams &cp, const twed_params *prm, const void *rowsX,
+                                    const int64_t *offX, int64_t nX, const void *rowsY, const int64_t *offY,
+                                    int64_t nY, const int64_t *pairs, int64_t nPairs, void *state,
+                                    int64_t maxlen, void *D, hipStream_t st)
+{
+    if (nPairs <= 0) return TWED_OK;
+    std::vector<int64_t> hp((size_t)nPairs * 2);
+    hipError_t e = hipMemcpyAsync(hp.data(), pairs, (size_t)nPairs * 16, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail_hip(e, "pair list read-back");
+    const int64_t kshort = twed_batch_max_short_length(prm->dim);
+    const size_t S = (size_t)row_stride(prec, cp.dimt), cs = cost_size(prec), as = acc_size(prec);
+    const int64_t nflags = (maxlen + 63) / 64, zero_words = nflags + kTailWords;
+    void *bnd = state;
+    uint32_t *flags = (uint32_t *)((char *)state + align_up((size_t)2 * (size_t)(maxlen + 1) * 2 * as));
+    for (int64_t k = 0; k < nPairs; ++k) {
+        const int64_t i = hp[2 * k], j = hp[2 * k + 1];
+        if (i < 0 || i >= nX || j < 0 || j >= nY) continue;  // NaN, written by the batch kernel
+        const int64_t li = offX[i + 1] - offX[i], lj = offY[j + 1] - offY[j];
+        if (std::min(li, lj) <= kshort) continue;  // swept by the batch kernel
+        const char *ra = (const char *)rowsX + (size_t)(offX[i] + i) * S * cs;
+        const char *rb = (const char *)rowsY + (size_t)(offY[j] + j) * S * cs;
+        const bool swap = lj > li;  // the longer series streams
+        e = launch_zero32(flags, zero_words, st);
+        if (e != hipSuccess) return fail_hip(e, "flag reset launch");
+        twed_status s = run_pair_sweep(prec, cp, prm, swap ? rb : ra, swap ? ra : rb, swap ? lj : li,
+                                       swap ? li : lj, bnd, flags, flags + nflags, nullptr,
+                                       (char *)D + (size_t)k * as, nullptr, st);
+        if (s != TWED_OK) return s;
+    }
+    return TWED_OK;
+}
+
+}  // namespace capi
+}  // namespace twed
 
 extern "C" {
 
@@ -628,7 +740,7 @@ static twed_status twed_pair_tune_body(const void *A, const void *TA, int64_t nA
     if (best.K == 0) return fail(TWED_ERR_UNSUPPORTED, "no sweep configuration fits this pair");
     {
         std::lock_guard<std::mutex> lock(tune_mutex());
-        tune_cache()[TuneKey{(int)prec, cp.dimt, cp.pm, nB}] = best;
+        tune_cache()[TuneKey{device_id(), (int)prec, cp.dimt, cp.pm, nB}] = best;
     }
     if (strip_k) *strip_k = best.K;
     if (group) *group = best.G;
@@ -648,6 +760,7 @@ void twed_tune_clear(void)
 {
     std::lock_guard<std::mutex> lock(tune_mutex());
     tune_cache().clear();
+    batch_cache().clear();
 }
 
 int64_t twed_batch_max_short_length(int32_t dim)
@@ -772,6 +885,205 @@ twed_status twed_batch_plan_stage_y(twed_batch_plan *plan, const void *Y, const 
 }
 
 void twed_batch_plan_destroy(twed_batch_plan *plan) { delete plan; }
+
+twed_status twed_batch_plan_config(const twed_batch_plan *plan, int32_t *chunk, int32_t *waves_per_cu,
+                                   int32_t *lane_mode)
+{
+    last_error().clear();
+    if (!plan) return fail(TWED_ERR_INVALID, "plan is NULL");
+    const BatchConfig &c = plan->p.cfg;
+    if (chunk) *chunk = c.chunk;
+    if (waves_per_cu) *waves_per_cu = c.waves_per_cu;
+    if (lane_mode) *lane_mode = c.lane_mode;
+    return TWED_OK;
+}
+
+static twed_status twed_batch_plan_tune_body(twed_batch_plan *plan, const void *X, const void *TX, const void *Y,
+                                             const void *TY, const int64_t *pairs, void *D, hipStream_t st,
+                                             int32_t *chunk, int32_t *waves_per_cu, int32_t *lane_mode)
+{
+    twed_status s = twed_batch_plan_run(plan, X, TX, Y, TY, pairs, D, st);  // validates; warm-up run
+    if (s != TWED_OK) return s;
+    BatchPlan &P = plan->p;
+    const BatchConfig start = P.cfg;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess) {
+        if (ev0) hipEventDestroy(ev0);
+        return fail_hip(e, "event create");
+    }
+    // time of one run under configuration c (median of three)
+    auto time_of = [&](const BatchConfig &c, float *ms_out) -> twed_status {
+        P.cfg = c;
+        float t[3];
+        for (int r = 0; r < 3; ++r) {
+            if ((e = hipEventRecord(ev0, st)) != hipSuccess) return fail_hip(e, "event record");
+            twed_status s2 = batch_enqueue(P, X, TX, Y, TY, pairs, D, st);
+            if (s2 != TWED_OK) return s2;
+            if ((e = hipEventRecord(ev1, st)) != hipSuccess || (e = hipEventSynchronize(ev1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&t[r], ev0, ev1)) != hipSuccess)
+                return fail_hip(e, "tuning run");
+        }
+        std::sort(t, t + 3);
+        *ms_out = t[1];
+        return TWED_OK;
+    };
+    BatchConfig best{};
+    float best_ms = 0.f;
+    auto consider = [&](const BatchConfig &c) -> twed_status {
+        float ms = 0.f;
+        twed_status s2 = time_of(c, &ms);
+        if (s2 != TWED_OK) return s2;
+        if (best_ms == 0.f || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+        return TWED_OK;
+    };
+    // coordinate search: the rule's configuration, then the lane mode of a
+    // single short query, the items per ticket, the resident waves per CU
+    s = consider(BatchConfig{});
+    if (s == TWED_OK && lane_eligible(P)) s = consider(BatchConfig{0, 0, 0});
+    const bool lanes = lane_eligible(P) && best.lane_mode != 0;
+    if (s == TWED_OK && !lanes) {
+        const int64_t items = batch_items(P);
+        for (int c : {1, 2, 4, 8, 16, 32, 64}) {
+            if (c > 1 && c > items) break;
+            BatchConfig t = best;
+            t.chunk = c;
+            if ((s = consider(t)) != TWED_OK) break;
+        }
+    }
+    if (s == TWED_OK) {
+        const int cus = std::max(1, device_simds() / 4);
+        const int per_cu = batch_max_workers(P.prec, P.cp) / cus;
+        for (int w : {per_cu / 4, per_cu / 2, (3 * per_cu) / 4}) {
+            if (w < 1) continue;
+            BatchConfig t = best;
+            t.waves_per_cu = w;
+            if ((s = consider(t)) != TWED_OK) break;
+        }
+    }
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+    if (s != TWED_OK) {
+        P.cfg = start;
+        return s;
+    }
+    P.cfg = best;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        batch_cache()[P.key] = best;
+    }
+    if (chunk) *chunk = best.chunk;
+    if (waves_per_cu) *waves_per_cu = best.waves_per_cu;
+    if (lane_mode) *lane_mode = best.lane_mode;
+    return TWED_OK;
+}
+
+twed_status twed_batch_plan_tune(twed_batch_plan *plan, const void *X, const void *TX, const void *Y, const void *TY,
+                                 const int64_t *pairs, void *D, hipStream_t stream, int32_t *chunk,
+                                 int32_t *waves_per_cu, int32_t *lane_mode)
+{
+    last_error().clear();
+    return no_throw([&] {
+        return twed_batch_plan_tune_body(plan, X, TX, Y, TY, pairs, D, stream, chunk, waves_per_cu, lane_mode);
+    });
+}
+
+// Tuning cache file: a header line, then one line per entry,
+//   pair  <device> <precision> <dimt> <pm> <nB> <K> <G> <sub_shift>
+//   batch <device> <precision> <dimt> <pm> <mode> <lx> <ly> <items> <chunk> <waves_per_cu> <lane_mode>
+static const char kTuneHeader[] = "libtwed-tune 1";
+
+static twed_status twed_tune_save_body(const char *path)
+{
+    if (!path) return fail(TWED_ERR_INVALID, "path is NULL");
+    std::string text = std::string(kTuneHeader) + "\n";
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        char line[512];
+        for (const auto &kv : tune_cache()) {
+            const auto &k = kv.first;
+            std::snprintf(line, sizeof line, "pair %s %d %d %d %lld %d %d %d\n", std::get<0>(k).c_str(),
+                          std::get<1>(k), std::get<2>(k), std::get<3>(k), (long long)std::get<4>(k), kv.second.K,
+                          kv.second.G, kv.second.sub_shift);
+            text += line;
+        }
+        for (const auto &kv : batch_cache()) {
+            const auto &k = kv.first;
+            std::snprintf(line, sizeof line, "batch %s %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k).c_str(),
+                          std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
+                          std::get<6>(k), std::get<7>(k), kv.second.chunk, kv.second.waves_per_cu,
+                          kv.second.lane_mode);
+            text += line;
+        }
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(TWED_ERR_INVALID, "cannot open the tuning cache file for writing");
+    const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (std::fclose(f) != 0 || !ok) return fail(TWED_ERR_INVALID, "cannot write the tuning cache file");
+    return TWED_OK;
+}
+
+twed_status twed_tune_save(const char *path)
+{
+    last_error().clear();
+    return no_throw([&] { return twed_tune_save_body(path); });
+}
+
+static twed_status twed_tune_load_body(const char *path)
+{
+    if (!path) return fail(TWED_ERR_INVALID, "path is NULL");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(TWED_ERR_INVALID, "cannot open the tuning cache file");
+    std::map<TuneKey, SweepChoice> pairs;
+    std::map<BatchKey, BatchConfig> batches;
+    char line[512];
+    bool header = false, bad = false;
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        if (!header) {
+            header = l == kTuneHeader;
+            if (!header) bad = true;
+            if (bad) break;
+            continue;
+        }
+        if (l.empty()) continue;
+        char kind[16], dev[128];
+        int a[10];
+        long long n = 0;
+        if (std::sscanf(l.c_str(), "%15s", kind) != 1) { bad = true; break; }
+        if (std::strcmp(kind, "pair") == 0 &&
+            std::sscanf(l.c_str(), "pair %127s %d %d %d %lld %d %d %d", dev, &a[0], &a[1], &a[2], &n, &a[3], &a[4],
+                        &a[5]) == 8 &&
+            (a[3] == 1 || a[3] == 2 || a[3] == 4 || a[3] == 8) && (a[4] == 1 || a[4] == 4 || a[4] == 8) &&
+            a[5] >= 3 && a[5] <= 5) {
+            pairs[TuneKey{dev, a[0], a[1], a[2], (int64_t)n}] = SweepChoice{a[3], a[4], a[5]};
+        } else if (std::strcmp(kind, "batch") == 0 &&
+                   std::sscanf(l.c_str(), "batch %127s %d %d %d %d %d %d %d %d %d %d", dev, &a[0], &a[1], &a[2],
+                               &a[3], &a[4], &a[5], &a[6], &a[7], &a[8], &a[9]) == 11 &&
+                   a[7] >= 0 && a[7] <= 4096 && a[8] >= 0 && a[8] <= 64 && a[9] >= -1 && a[9] <= 1) {
+            batches[BatchKey{dev, a[0], a[1], a[2], a[3], a[4], a[5], a[6]}] = BatchConfig{a[7], a[8], a[9]};
+        } else {
+            bad = true;
+            break;
+        }
+    }
+    std::fclose(f);
+    if (bad || !header) return fail(TWED_ERR_INVALID, "malformed tuning cache file");
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    for (const auto &kv : pairs) tune_cache()[kv.first] = kv.second;
+    for (const auto &kv : batches) batch_cache()[kv.first] = kv.second;
+    return TWED_OK;
+}
+
+twed_status twed_tune_load(const char *path)
+{
+    last_error().clear();
+    return no_throw([&] { return twed_tune_load_body(path); });
+}
 
 const char *twed_status_string(twed_status s)
 {

@@ -138,9 +138,10 @@ def test_batch_argument_errors(L):
     assert _batch(L, prm, [0, 3, 5], nY=2, TY=FAKE) == INVALID
     assert _batch(L, prm, [0, 3, 5], offY=[0, 2], nY=1, Y=FAKE, TY=None) == INVALID
     assert _batch(L, prm, [0, 3, 5], offY=[0, 2], nY=1, Y=FAKE, TY=FAKE, pairs=FAKE, nP=-1) == INVALID
-    # pair list with both collections holding over-long series
+    # pair list with both collections holding over-long series: accepted
+    # (such pairs run the single-pair sweep); here only the workspace is missing
     longs = [0, 5000, 10000]
-    assert _batch(L, prm, longs, offY=longs, nY=2, Y=FAKE, TY=FAKE, pairs=FAKE, nP=1) == UNSUPPORTED
+    assert _batch(L, prm, longs, offY=longs, nY=2, Y=FAKE, TY=FAKE, pairs=FAKE, nP=1) == WORKSPACE
     need = L.twed_batch_workspace_size(np.array([0, 3, 5], np.int64).ctypes.data_as(binding._i64p), 2,
                                        None, 0, ctypes.byref(prm))
     assert need > 0
@@ -156,6 +157,25 @@ def test_batch_max_short_length(L):
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError, match="not built"):
         binding.load_library(str(tmp_path / "nope.so"))
+
+
+def test_embed_limits_bound_the_workspace(L):
+    import ctypes as C
+    off = np.arange(0, 1_000_001, 500, dtype=np.int64)  # 2000 series of 500 samples
+    po = off.ctypes.data_as(C.POINTER(C.c_int64))
+    try:
+        full = L.twed_embed_workspace_size(po, 2000, 0)
+        L.twed_embed_set_limits(10_000, 0)
+        small = L.twed_embed_workspace_size(po, 2000, 0)
+        L.twed_embed_set_limits(100, 0)  # below the longest series: one series per chunk
+        tiny = L.twed_embed_workspace_size(po, 2000, 0)
+        # activations are about 0.3 KB per sample of the chunk
+        assert full - small > 250 * (1_000_000 - 10_000)
+        assert small - tiny > 250 * (10_000 - 500)
+        assert tiny > 0
+    finally:
+        L.twed_embed_set_limits(0, 0)
+    assert L.twed_embed_workspace_size(po, 2000, 0) == full
 
 
 def test_embed_and_knn_host_checks(L):
@@ -300,3 +320,28 @@ def test_batch_plan_host_checks(L):
     assert L.twed_batch_plan_run(None, FAKE, FAKE, None, None, None, FAKE, None) == INVALID
     assert L.twed_batch_plan_stage_y(None, FAKE, FAKE, None) == INVALID
     L.twed_batch_plan_destroy(None)
+
+
+def test_tune_cache_file_round_trip(L, tmp_path):
+    # the tuning cache file: entries written by hand load, save back the
+    # same, and a malformed file is refused without changing the cache
+    L.twed_tune_clear()
+    src = tmp_path / "in.txt"
+    lines = ["libtwed-tune 1",
+             "pair gfx950-cu256 2 8 1 1000000 8 8 4",
+             "batch gfx950-cu256 1 1 0 0 9 9 21 8 16 -1"]
+    src.write_text("\n".join(lines) + "\n")
+    assert L.twed_tune_load(bytes(str(src), "utf-8")) == 0
+    out = tmp_path / "out.txt"
+    assert L.twed_tune_save(bytes(str(out), "utf-8")) == 0
+    assert out.read_text().splitlines() == lines
+    bad = tmp_path / "bad.txt"
+    bad.write_text("libtwed-tune 1\npair gfx950-cu256 2 8 1 1000000 3 8 4\n")  # K = 3 is not a strip width
+    assert L.twed_tune_load(bytes(str(bad), "utf-8")) == INVALID
+    assert L.twed_tune_load(bytes(str(tmp_path / "missing.txt"), "utf-8")) == INVALID
+    out2 = tmp_path / "out2.txt"
+    assert L.twed_tune_save(bytes(str(out2), "utf-8")) == 0
+    assert out2.read_text().splitlines() == lines
+    L.twed_tune_clear()
+    assert L.twed_tune_save(bytes(str(out2), "utf-8")) == 0
+    assert out2.read_text().splitlines() == ["libtwed-tune 1"]

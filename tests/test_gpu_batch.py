@@ -310,3 +310,75 @@ def test_batch_plan_staged_collection(prec, dim, nq):
         torch.cuda.synchronize()
         assert np.array_equal(D.cpu().numpy(), want[i]), i
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pair_list_with_long_series(prec):
+    # Pair lists whose pairs hold two series longer than one wave's strip run
+    # those pairs through the single-pair sweep: every entry equals twed_pair
+    # bit for bit, short pairs stay in the batch kernel, invalid entries are NaN.
+    rng = np.random.default_rng(21)
+    lx, ly = [50, 1100, 2000, 700], [1500, 70, 1030, 4000]
+    cx = synth.pack([synth.walk(rng, L, 1) for L in lx], [synth.irregular_times(rng, L) for L in lx])
+    cy = synth.pack([synth.walk(rng, L, 1) for L in ly], [synth.irregular_times(rng, L) for L in ly])
+    Xd, TXd = to_dev(cx, prec)
+    Yd, TYd = to_dev(cy, prec)
+    prs = [(1, 0), (2, 3), (0, 1), (3, 2), (1, 2), (-1, 0), (2, 0), (0, 3), (3, 9)]
+    P = torch.as_tensor(np.array(prs, dtype=np.int64), device="cuda")
+    say(f"pair list with long series {prec}: {len(prs)} pairs")
+    D = tw.twed_batch(Xd, TXd, cx.off, Yd, TYd, cy.off, pairs=P, nu=1e-3, lam=1.0, p=1.0,
+                      precision=prec).cpu().numpy()
+    Xr, TXr = ref_inputs(cx, prec)
+    Yr, TYr = ref_inputs(cy, prec)
+    for k, (i, j) in enumerate(prs):
+        if not (0 <= i < len(lx) and 0 <= j < len(ly)):
+            assert np.isnan(D[k]), k
+            continue
+        a = slice(cx.off[i], cx.off[i + 1])
+        b = slice(cy.off[j], cy.off[j + 1])
+        one = tw.twed_pair(Xd[a], TXd[a], Yd[b], TYd[b], 1e-3, 1.0, 1.0, prec).item()
+        assert D[k] == one, (k, D[k], one)
+        ref = oracle.get().twed(Xr[a], TXr[a], Yr[b], TYr[b], 1e-3, 1.0, 1.0, rows=True)
+        assert abs(D[k] - ref) <= TOL[prec] * ref, k
+
+
+def test_batch_plan_tune_bitwise(tmp_path):
+    # The autotuner's runs and the tuned plan's runs give the untuned matrix
+    # bit for bit; the choice is cached under the plan's size class (a new plan
+    # of that class picks it up) and survives a save / clear / load cycle.
+    col = synth.batch_collection(300, 64, 1024, seed=31)
+    X, T = to_dev(col, "f32")
+    tw.twed_tune_clear()
+    plan = tw.BatchPlan(col.off, precision="f32")
+    assert plan.config() == (0, 0, -1)
+    D0 = plan.run(X, T).clone()
+    say("batch plan tune: 300 series")
+    Dt = plan.output()
+    choice = plan.tune(X, T, D=Dt)
+    say(f"  tuned (chunk, waves/CU, lane mode) = {choice}")
+    torch.cuda.synchronize()
+    assert torch.equal(Dt, D0)
+    assert plan.config() == choice
+    D1 = plan.run(X, T)
+    assert torch.equal(D1, D0)
+    plan2 = tw.BatchPlan(col.off, precision="f32")
+    assert plan2.config() == choice
+    path = tmp_path / "tune.txt"
+    tw.twed_tune_save(path)
+    tw.twed_tune_clear()
+    assert tw.BatchPlan(col.off, precision="f32").config() == (0, 0, -1)
+    tw.twed_tune_load(path)
+    plan3 = tw.BatchPlan(col.off, precision="f32")
+    assert plan3.config() == choice
+    assert torch.equal(plan3.run(X, T), D0)
+    # a single short query: the lane mode is one of the candidates
+    q = col.subset([5])
+    qs = synth.pack([q.X[:20]], [q.T[:20]])
+    Q, TQ = to_dev(qs, "f32")
+    qplan = tw.BatchPlan(qs.off, col.off, precision="f32")
+    R0 = qplan.run(Q, TQ, X, T).clone()
+    qplan.tune(Q, TQ, X, T)
+    assert torch.equal(qplan.run(Q, TQ, X, T), R0)
+    for p in (plan, plan2, plan3, qplan):
+        p.close()
+    tw.twed_tune_clear()

@@ -117,6 +117,60 @@ def test_forward_chunk_independence():
         np.testing.assert_array_equal(emb_i[0], emb_all[i])
 
 
+@pytest.fixture
+def limits():
+    """Sets twed_embed_set_limits for one test and restores the defaults."""
+    yield B.twed_embed_set_limits
+    B.twed_embed_set_limits(0, 0)
+
+
+def test_forward_many_chunks_bitwise(limits):
+    # A collection embedded in many small chunks (each a run of whole series
+    # from a nonzero base row) equals the single-chunk forward bit for bit.
+    # Chunks after the first start at row_base > 0: a segment length or row
+    # index taken relative to the wrong base would read outside the chunk's
+    # activations here.
+    c = synth.knn_collection(60, 5)
+    X, off = c.X.reshape(-1).astype(np.float32), c.off
+    vec, params = random_params(4)
+    ref = B.twed_embed_forward(dev(vec), dev(X), off).cpu().numpy()
+    for rows in (600, 1500):
+        limits(rows, 0)
+        say(f"forward in chunks of {rows} rows: {c.count} series, {off[-1]} rows")
+        got = B.twed_embed_forward(dev(vec), dev(X), off).cpu().numpy()
+        np.testing.assert_array_equal(got, ref)
+    limits(0, 0)
+    picks = [c.count - 1, c.count // 2]
+    want = ocnn.embed(params, [X[off[i]:off[i + 1]].astype(np.float64) for i in picks])
+    for j, i in enumerate(picks):
+        assert rel_norm(ref[i], want[j]) < 3e-2, i
+
+
+def test_forward_default_chunk_boundary():
+    # At the default limit (2^22 samples per chunk) a collection of 4.6e6
+    # samples is embedded in two chunks; series of the second chunk agree bit
+    # for bit with the same series embedded alone, and with the FP64 oracle.
+    rng = np.random.default_rng(11)
+    lengths = rng.integers(384, 641, 9000)
+    off = np.zeros(len(lengths) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lengths)
+    assert off[-1] > (1 << 22) + 100_000
+    X = np.cumsum(rng.standard_normal(off[-1]).astype(np.float32)).astype(np.float32)
+    X -= np.repeat(X[off[:-1]], lengths)  # every series starts near 0
+    vec, params = random_params(5)
+    say(f"forward at the default chunk: {len(lengths)} series, {off[-1]} rows")
+    emb = B.twed_embed_forward(dev(vec), dev(X), off).cpu().numpy()
+    first2 = int(np.searchsorted(off, 1 << 22, side="right"))  # a series of the second chunk
+    picks = [0, first2 - 2, first2 - 1, first2, first2 + 1, len(lengths) - 1]
+    for i in picks:
+        Xi = X[off[i]:off[i + 1]]
+        alone = B.twed_embed_forward(dev(vec), dev(Xi), np.array([0, len(Xi)], np.int64)).cpu().numpy()
+        np.testing.assert_array_equal(alone[0], emb[i])
+    want = ocnn.embed(params, [X[off[i]:off[i + 1]].astype(np.float64) for i in picks[-3:]])
+    for j, i in enumerate(picks[-3:]):
+        assert rel_norm(emb[i], want[j]) < 3e-2, i
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_loss_and_gradients_match_oracle(seed):
     series = ragged_series(seed + 10)
@@ -234,6 +288,32 @@ def test_knn_exhaustive_is_exact():
     ix.close()
 
 
+def test_knn_many_chunks_matches_single(limits):
+    # index build and queries forced through many forward chunks and score
+    # chunks (three queries per score chunk) give the default-limit answer
+    # bit for bit; the exhaustive form stays exact against the oracle
+    db, DB, TDB = collection(300, 3)
+    qc, Q, TQ = collection(10, 4)
+    vec = knn.init_params(3)
+    runs = {}
+    for name, lim in (("default", (0, 0)), ("chunked", (900, 3 * db.count * 4))):
+        limits(*lim)
+        ix = index_for(DB, TDB, db.off, vec)
+        for n_cand in (40, db.count):
+            say(f"knn {name}: n_cand {n_cand}")
+            ids, dist = ix.query(dev(Q), dev(TQ), qc.off, k=10, n_cand=n_cand)
+            runs[name, n_cand] = (ids.cpu().numpy(), dist.cpu().numpy())
+        ix.close()
+    for n_cand in (40, db.count):
+        np.testing.assert_array_equal(runs["chunked", n_cand][0], runs["default", n_cand][0])
+        np.testing.assert_array_equal(runs["chunked", n_cand][1], runs["default", n_cand][1])
+    ids, dist = runs["chunked", db.count]
+    pairs = np.array([(q, j) for q in range(qc.count) for j in range(db.count)], dtype=np.int64)
+    D = oracle_dists(Q, TQ, qc.off, DB, TDB, db.off, pairs).reshape(qc.count, db.count)
+    for q in range(qc.count):
+        np.testing.assert_allclose(dist[q], np.sort(D[q])[:10], rtol=1e-5)
+
+
 def test_knn_pruned_candidates():
     db, DB, TDB = collection(300, 3)
     qc, Q, TQ = collection(8, 4)
@@ -292,3 +372,28 @@ def test_training_lowers_loss_and_helps_recall():
     say(f"recall@10: {rec}")
     assert rec["trained@150"] >= rec["untrained@150"]
     assert rec["trained@150"] > rec["trained_network_only"]
+
+
+def test_knn_long_series_exhaustive():
+    # queries and database series longer than one wave's strip (1,024
+    # samples): their pairs run the single-pair sweep; the exhaustive answer
+    # is exact against the oracle
+    rng = np.random.default_rng(41)
+    lens_db = [1030, 1200, 300, 1500, 1100, 900, 2000, 1025]
+    lens_q = [1300, 200]
+    mk = lambda L: np.cumsum(rng.standard_normal(L)).astype(np.float32)
+    DBs, Qs = [mk(L) for L in lens_db], [mk(L) for L in lens_q]
+    DB, offDB = pack(DBs)
+    Q, offQ = pack(Qs)
+    TDB = np.concatenate([np.arange(L, dtype=np.float32) for L in lens_db])
+    TQ = np.concatenate([np.arange(L, dtype=np.float32) for L in lens_q])
+    ix = index_for(DB, TDB, offDB, knn.init_params(5))
+    say("knn long series: 8 db, 2 queries")
+    ids, dist = ix.query(dev(Q), dev(TQ), offQ, k=4, n_cand=len(lens_db))
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    ix.close()
+    pairs = np.array([(q, j) for q in range(len(lens_q)) for j in range(len(lens_db))], dtype=np.int64)
+    D = oracle_dists(Q, TQ, offQ, DB, TDB, offDB, pairs).reshape(len(lens_q), len(lens_db))
+    for q in range(len(lens_q)):
+        np.testing.assert_allclose(dist[q], np.sort(D[q])[:4], rtol=1e-5)
+        np.testing.assert_allclose(D[q, ids[q]], dist[q], rtol=1e-5)
