@@ -113,6 +113,29 @@ twed_status twed_pair(const void *A, const void *TA, int64_t nA,
                       const twed_params *prm, void *out,
                       void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as twed_pair, bitwise equal to it, with no workspace argument.
+ * Its scratch memory is a fixed array of TWED_PAIR_NOALLOC_SCRATCH_BYTES
+ * bytes inside the library, one per GPU, held until the process ends; the
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  The first call on a device looks up that device's copy of the
+ * array (hipGetSymbolAddress), so make the device current as for any HIP call.
+ * Every call on one GPU shares its array, and the staging kernel clears what
+ * must start at zero: calls on one GPU whose work overlaps (different streams
+ * without ordering, other host threads) race and give wrong results; calls
+ * ordered on one stream are safe.  Arguments and errors as twed_pair, plus
+ * TWED_ERR_UNSUPPORTED (with a message naming the size) when the pair needs
+ * more than TWED_PAIR_NOALLOC_SCRATCH_BYTES, i.e. when
+ * twed_pair_workspace_size(nA, nB, prm) exceeds it.  Equal lengths that fit:
+ * up to 698,495 samples (1-D F64), 1,396,183 (1-D F32), 523,927 (3-D F64 or
+ * 8-D F32_ACC64). */
+#define TWED_PAIR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+twed_status twed_pair_noalloc(const void *A, const void *TA, int64_t nA,
+                              const void *B, const void *TB, int64_t nB,
+                              const twed_params *prm, void *out, hipStream_t stream);
+
 /* Same as twed_pair, and also writes every DP cell to `dp` (device,
  * (nA+1)*(nB+1) elements of the result type, row-major, row stride nB+1,
  * row 0 and column 0 included).  Meant for validation on small problems:

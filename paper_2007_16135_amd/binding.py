@@ -20,7 +20,7 @@ TWED_OK, TWED_ERR_INVALID, TWED_ERR_UNSUPPORTED, TWED_ERR_WORKSPACE, TWED_ERR_DE
 PRECISIONS = {"f64": 0, "f32": 1, "f32_acc64": 2, "auto": 3}
 ALGOS = {"auto": 0, "wavefront": 1, "diagonal": 2}
 EXPORTS = [
-    "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_matrix",
+    "twed_params_default", "twed_pair_workspace_size", "twed_pair", "twed_pair_noalloc", "twed_pair_matrix",
     "twed_batch_workspace_size", "twed_batch", "twed_batch_max_short_length",
     "twed_batch_plan_create", "twed_batch_plan_run", "twed_batch_plan_destroy", "twed_batch_plan_stage_y",
     "twed_batch_plan_tune", "twed_batch_plan_config", "twed_tune_save", "twed_tune_load",
@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH):
     L.twed_pair_workspace_size.restype = ctypes.c_size_t
     L.twed_pair.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, _vp, ctypes.c_size_t, _vp]
     L.twed_pair.restype = ctypes.c_int
+    L.twed_pair_noalloc.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, _vp]
+    L.twed_pair_noalloc.restype = ctypes.c_int
     L.twed_pair_matrix.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.twed_pair_matrix.restype = ctypes.c_int
     L.twed_batch_workspace_size.argtypes = [_i64p, _i64, _i64p, _i64, _pp]
@@ -252,6 +254,22 @@ def twed_pair(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", algo="auto
         out = torch.empty(1, dtype=output_dtype(precision), device=A2.device)
     _check(L.twed_pair(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
                        ctypes.byref(prm), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out
+
+
+def twed_pair_noalloc(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", algo="auto", strip_k=0,
+                      acc64_threshold=0, out=None, stream=None):
+    """twed_pair without a workspace: the library's fixed per-device scratch
+    array (TWED_PAIR_NOALLOC_SCRATCH_BYTES) serves as one; calls that overlap
+    on one GPU race.  `out` (one element, float32 for "f32", float64
+    otherwise) is allocated here only when not given."""
+    torch = _torch()
+    A2, B2, nA, nB, dim = _pair_operands(A, TA, B, TB, precision)
+    prm = make_params(nu, lam, p, dim, precision, algo, strip_k, acc64_threshold)
+    if out is None:
+        out = torch.empty(1, dtype=output_dtype(precision), device=A2.device)
+    _check(load_library().twed_pair_noalloc(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB,
+                                            ctypes.byref(prm), out.data_ptr(), _stream(stream)))
     return out
 
 

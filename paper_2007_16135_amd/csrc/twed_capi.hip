@@ -257,14 +257,23 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     return TWED_OK;
 }
 
-twed_status pair_impl(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
-                      const twed_params *prm, void *out, void *dp, void *ws, size_t ws_bytes, hipStream_t st)
+// Argument checks of a single-pair call (no HIP call).
+twed_status check_pair_args(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                            const twed_params *prm, const void *out)
 {
     twed_status s = check_params(prm);
     if (s != TWED_OK) return s;
     if (!A || !TA || !B || !TB || !out) return fail(TWED_ERR_INVALID, "NULL array argument");
     if (nA < 1 || nB < 1) return fail(TWED_ERR_INVALID, "series lengths must be >= 1");
     if (nA > kMaxLen || nB > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    return TWED_OK;
+}
+
+twed_status pair_impl(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,
+                      const twed_params *prm, void *out, void *dp, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    twed_status s = check_pair_args(A, TA, nA, B, TB, nB, prm, out);
+    if (s != TWED_OK) return s;
     const Prec prec = resolve(prm, std::max(nA, nB));
     const PairLayout need = pair_layout(nullptr, nA, nB, prm, prec);
     s = check_workspace(ws, ws_bytes, need.total);
@@ -293,6 +302,44 @@ twed_status pair_impl(const void *A, const void *TA, int64_t nA, const void *B, 
         e = launch_widen((const float *)kout, (double *)out, 1, st);
         if (e != hipSuccess) return fail_hip(e, "widen launch");
     }
+    return TWED_OK;
+}
+
+// ---- the scratch array of the no-allocation pair call ---------------------------------
+//
+// One fixed device array per GPU stands in for the caller's workspace, so that
+// callers that cannot allocate (code under graph capture, serving loops)
+// still have one.  Host code never passes the array's name to a kernel: the
+// name is a host-side stand-in, and the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kNoAllocBytes = TWED_PAIR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+
+std::mutex &scratch_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
+// Device address of `scratch` on the current device.
+twed_status noalloc_scratch(void **out)
+{
+    static void *addr[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(TWED_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(scratch_mutex());
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p) % kAlign) return fail(TWED_ERR_DEVICE, "scratch array address not 256-byte aligned");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
     return TWED_OK;
 }
 
@@ -665,6 +712,26 @@ twed_status twed_pair(const void *A, const void *TA, int64_t nA, const void *B, 
 {
     last_error().clear();
     return pair_impl(A, TA, nA, B, TB, nB, prm, out, nullptr, workspace, ws_bytes, stream);
+}
+
+twed_status twed_pair_noalloc(const void *A, const void *TA, int64_t nA, const void *B, const void *TB,
+                              int64_t nB, const twed_params *prm, void *out, hipStream_t stream)
+{
+    last_error().clear();
+    twed_status s = check_pair_args(A, TA, nA, B, TB, nB, prm, out);
+    if (s != TWED_OK) return s;
+    const size_t need = pair_layout(nullptr, nA, nB, prm, resolve(prm, std::max(nA, nB))).total;
+    if (need > kNoAllocBytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg,
+                      "pair needs %zu bytes of scratch; twed_pair_noalloc holds %zu (use twed_pair with a workspace)",
+                      need, kNoAllocBytes);
+        return fail(TWED_ERR_UNSUPPORTED, msg);
+    }
+    void *ws = nullptr;
+    s = noalloc_scratch(&ws);
+    if (s != TWED_OK) return s;
+    return pair_impl(A, TA, nA, B, TB, nB, prm, out, nullptr, ws, kNoAllocBytes, stream);
 }
 
 twed_status twed_pair_matrix(const void *A, const void *TA, int64_t nA, const void *B, const void *TB, int64_t nB,

@@ -89,6 +89,27 @@ def test_pair_argument_errors(L):
     assert L.twed_last_error()
 
 
+def test_pair_noalloc_host_checks(L):
+    # argument errors as twed_pair; a pair whose workspace exceeds the fixed
+    # scratch array is refused, with the sizes in the message, before any HIP
+    # call
+    good = tw.make_params()
+    call = lambda prm, nA=10, nB=10, A=FAKE, out=FAKE: L.twed_pair_noalloc(
+        A, FAKE, nA, FAKE, FAKE, nB, ctypes.byref(prm) if prm is not None else None, out, None)
+    assert call(None) == INVALID
+    assert call(good, nA=0) == INVALID
+    assert call(good, A=None) == INVALID
+    assert call(good, out=None) == INVALID
+    assert call(tw.make_params(nu=-1.0)) == INVALID
+    assert call(tw.make_params(dim=33)) == UNSUPPORTED
+    limit = 64 << 20
+    big = 1 << 21
+    assert L.twed_pair_workspace_size(big, big, ctypes.byref(good)) > limit
+    assert call(good, nA=big, nB=big) == UNSUPPORTED
+    msg = L.twed_last_error().decode()
+    assert "twed_pair_noalloc" in msg and str(limit) in msg
+
+
 def test_pair_matrix_needs_dp(L):
     good = tw.make_params()
     assert L.twed_pair_matrix(FAKE, FAKE, 4, FAKE, FAKE, 4, ctypes.byref(good), FAKE, None, None, 0,
