@@ -6,12 +6,17 @@ Headline workload: one pair of 8-D Gaussian random walks, n = m = 1,000,000
 costs with FP64 accumulators, inputs resident in device memory.  One step is
 one full twed_pair call (staging + the wavefront sweep, 10^12 cells).
 
-Also reported (secondary, not the headline value): the batched all-pairs
-distance matrix of 2,048 1-D FP32 walks with lengths uniform in [64, 1024].
+Also reported (secondary, not the headline value): the same pair in FP64;
+the 3-D n = 1e5 pair (FP64 and FP32); the batched all-pairs distance matrix
+of 2,048 1-D FP32 walks with lengths uniform in [64, 1024]; one column shard,
+an alignment path, LCS and DTW on the band sweep; one R^28 query against
+60,000 series; the paper's own shapes; the learned k-NN search (1e5-series
+database, 1e4 queries: recall@10 against exhaustive TWED, queries/s).
 
 Printed: ONE JSON line with metric, value (GCUPS), timing, the roofline of the
-dominant kernel (VALU-bound: lane operations per cell x cells / kernel time vs
-the chip's VALU lane rate) and the CPU oracle timed on a bounded sample.
+dominant kernel (VALU-bound: the cell-rate ceiling of its operation mix at the
+published FP32 / FP64 vector rates, with the fraction against the rates probed
+on the device beside it) and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -26,28 +31,66 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# Peak VALU lane rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# (one full-rate FP32 or FP64 lane operation per lane per clock, no packed
-# math); 78.6 TFLOP/s FP64 vector = this rate x 2 flops per FMA.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Published vector rates of MI355X (256 CUs at 2.4 GHz): FP32 vector 157.3
+# TFLOP/s and FP64 vector 78.6 TFLOP/s, i.e. 78.6 T and 39.3 T lane operations
+# per second (an FMA is one lane operation, two flops).  Transcendentals (the
+# FP32 square root) run at a quarter of the FP32 rate.  The FP64 square root
+# (correctly rounded: a reciprocal-root seed and refinement steps) is priced
+# as one quarter-rate FP64 operation.  Every HIP file is compiled without
+# packed FP32 instructions.
+RATES_PUBLISHED = {"f32": 157.3 / 2, "f32_trans": 157.3 / 8, "f64": 78.6 / 2, "f64_sqrt": 78.6 / 8}
 
-# Algorithmic VALU lane operations per DP cell (see the design notes):
-#   8-D L2 distance in f32: 8 sub + 1 mul + 7 fma + sqrt (quarter rate: 4) = 20
-#   time term: sub + fma = 2;   f32 -> f64 convert = 1
-#   f64: match add, up + del_A, left + del_B, X update add, 2 min = 6
-OPS_PER_CELL_8D_L2_ACC64 = 29
-#   1-D L1 in f32: value sub, time sub, fma (|.| are free source modifiers),
-#   match add, two deletion adds, one three-way min (v_min3_f32 is a single
-#   full-rate instruction), X add = 8
-OPS_PER_CELL_1D_L1_F32 = 8
-#   3-D L2: 3 sub + 1 mul + 2 fma + sqrt (4) = 10; time sub + fma = 2; then
-#   FP64 accumulators: match add, two deletion adds, two min, X add = 6 (18);
-#   FP32 accumulators: the three-way min is one v_min3_f32 (17)
-OPS_PER_CELL_3D_L2_F64 = 18
-OPS_PER_CELL_3D_L2_F32 = 17
-#   1-D L1 in f64: value sub, time sub, fma; match add, two deletion adds,
-#   two min (no three-way f64 min), X add = 9
-OPS_PER_CELL_1D_L1_F64 = 9
+# Algorithmic VALU lane operations per DP cell, by rate class:
+#   8-D L2 distance in f32: 8 sub + 1 mul + 7 fma, then the root (f32_trans);
+#   time term: sub + fma (|.| is a free source modifier); f32 -> f64 convert;
+#   f64 accumulators: match add, up + del_A, left + del_B, X add, two min
+#   (there is no three-way f64 min).
+MIX_8D_L2_ACC64 = {"f32": 18, "f32_trans": 1, "f64": 7}
+#   1-D L1 in f32: value sub, time sub, fma, match add, two deletion adds,
+#   one three-way min (v_min3_f32), X add.
+MIX_1D_L1_F32 = {"f32": 8}
+#   3-D L2 in f64: 3 sub + 1 mul + 2 fma, root, time sub + fma, 6 accumulator ops.
+MIX_3D_L2_F64 = {"f64": 14, "f64_sqrt": 1}
+#   3-D L2 in f32: 3 sub + 1 mul + 2 fma, root, time sub + fma, match add, two
+#   deletion adds, one three-way min, X add.
+MIX_3D_L2_F32 = {"f32": 13, "f32_trans": 1}
+#   1-D L1 in f64: value sub, time sub, fma, 6 accumulator ops.
+MIX_1D_L1_F64 = {"f64": 9}
+#   28-D L2 in f64: 28 sub + 1 mul + 27 fma, root, time sub + fma, 6 accumulator ops.
+MIX_28D_L2_F64 = {"f64": 64, "f64_sqrt": 1}
+
+
+def mix_ops(mix):
+    return sum(mix.values())
+
+
+def ceiling_gcups(mix, rates):
+    """Cell-rate ceiling (GCUPS) of a cell with this operation mix when every
+    class issues at its rate (T lane-op/s) and the classes share the SIMDs."""
+    ps_per_cell = sum(n / rates[k] for k, n in mix.items())  # chip-wide picoseconds per cell
+    return 1e3 / ps_per_cell
+
+
+def measured_rates(peaks):
+    """Rates by class from the on-device probes (add / minimum chains for the
+    plain classes, the square-root chain for f32_trans)."""
+    return {"f32": peaks["f32_add_T_lane_op_s"], "f32_trans": peaks["f32_sqrt_T_lane_op_s"],
+            "f64": peaks["f64_add_T_lane_op_s"], "f64_sqrt": peaks["f64_add_T_lane_op_s"] / 4}
+
+
+def roofline_of(mix, gcups, peaks=None):
+    """Roofline fields of a VALU-bound sweep measured at `gcups`."""
+    ceil = ceiling_gcups(mix, RATES_PUBLISHED)
+    ops = mix_ops(mix)
+    out = {"bound": "alu", "achieved": round(ops * gcups / 1e3, 3), "peak": round(ops * ceil / 1e3, 3),
+           "unit": "T VALU lane-op/s", "frac": round(gcups / ceil, 4), "ops_per_cell": dict(mix),
+           "cell_rate_ceiling_GCUPS": round(ceil, 1)}
+    if peaks:
+        mceil = ceiling_gcups(mix, measured_rates(peaks))
+        out["frac_of_measured_peak"] = round(gcups / mceil, 4)
+        out["measured_cell_rate_ceiling_GCUPS"] = round(mceil, 1)
+    return out
+
 
 # The paper's single-pair timings (table "Raw Time to Solution", 1-D FP64,
 # most likely a P100; cuTWED_dev = device-resident inputs), seconds by N.
@@ -94,7 +137,7 @@ def parse():
     ap.add_argument("--rn-all", action="store_true", help="also time the 60000 x 60000 R^28 all-pairs matrix")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (counter calibration)")
-    ap.add_argument("--knn", action="store_true", help="also run the learned k-NN measurement")
+    ap.add_argument("--no-knn", action="store_true", help="skip the learned k-NN measurement")
     ap.add_argument("--no-peaks", action="store_true", help="skip the on-device VALU / HBM rate probes")
     ap.add_argument("--no-c2", action="store_true", help="skip the 3-D n=1e5 pair")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the headline pair")
@@ -105,7 +148,7 @@ def parse():
     ap.add_argument("--knn-queries", type=int, default=10_000, help="k-NN queries timed")
     ap.add_argument("--knn-truth", type=int, default=1000,
                     help="queries given exhaustive ground truth (recall sample)")
-    ap.add_argument("--knn-train-steps", type=int, default=500, help="training steps (2,048 pairs each)")
+    ap.add_argument("--knn-train-steps", type=int, default=5000, help="training steps (2,048 pairs each)")
     return ap.parse_args()
 
 
@@ -139,9 +182,10 @@ def measure_peaks(torch, dev):
     sink = torch.empty(waves * 64, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     out = {"compute_units": cus}
-    names = {0: "f32_fma", 1: "f32_add_min", 2: "f64_fma", 3: "f64_add_min"}
+    names = {0: "f32_fma", 1: "f32_add_min", 2: "f64_fma", 3: "f64_add_min", 4: "f32_sqrt", 5: "f32_add",
+             6: "f64_add", 7: "f32_min3"}
     for kind, name in names.items():
-        iters = 60000 if kind in (0, 2) else 30000
+        iters = 30000 if kind in (1, 3) else 60000
         ops = ctypes.c_double()
         best = None
         for _ in range(4):
@@ -171,7 +215,7 @@ def measure_peaks(torch, dev):
     out["hbm_copy_GB_s"] = round(2 * 4 * n / best / 1e9, 1)
     del src, dst, sink
     torch.cuda.empty_cache()
-    out["valu_lane_op_peak_derived_T"] = round(VALU_PEAK_TOPS, 3)
+    out["published_T_lane_op_s"] = {k: round(v, 3) for k, v in RATES_PUBLISHED.items()}
     return out
 
 
@@ -188,7 +232,7 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
 
     tr = knn.Trainer(dbc, nu, lam, seed=0, batch_series=256, pairs_per_step=2048, n_anchors=1024)
     log(f"knn: exact neighbours of 1024 anchors mined in {tr.mine_s:.1f} s")
-    train_s = tr.train(args.knn_train_steps, log_every=100, log=log)
+    train_s = tr.train(args.knn_train_steps, log_every=1000, log=log)
     params = tr.params.clone()
     t0 = time.perf_counter()
     index = B.KnnIndex(DB, TDB, db.off, params, nu, lam)
@@ -221,7 +265,7 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
 
     curve = {}
     chosen = None
-    for c in (200, 400, 800, 1600, 3200, 6400, 12800, 25600, 51200):
+    for c in (200, 400, 800, 1600, 3200, 6400, 9600, 12800, 16000, 19200, 25600, 38400, 51200):
         c = min(c, args.knn_db)
         curve[c] = recall(c)
         log(f"knn: recall@10 with {c} candidates: {curve[c]:.4f}")
@@ -274,8 +318,8 @@ def c2_bench(torch, tw, synth, dev, peaks):
     cells = float(n) * n
     out = {"workload": "single pair, 3-D random walks n=m=100000, irregular Exp(1) timestamps, nu=0.01, "
                        "lambda=0.5, L2", "cells_per_step": cells}
-    for prec, key, ops, gname in (("f64", "fp64", OPS_PER_CELL_3D_L2_F64, "walk3d_n100000"),
-                                  ("f32", "fp32", OPS_PER_CELL_3D_L2_F32, "walk3d_n100000_f32")):
+    for prec, key, mix, gname in (("f64", "fp64", MIX_3D_L2_F64, "walk3d_n100000"),
+                                  ("f32", "fp32", MIX_3D_L2_F32, "walk3d_n100000_f32")):
         dt = torch.float64 if prec == "f64" else torch.float32
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
         A, TA, B, TB = t(c.A), t(c.TA), t(c.B), t(c.TB)
@@ -288,11 +332,7 @@ def c2_bench(torch, tw, synth, dev, peaks):
         v = float(res.item())
         entry = {"ms": round(k * 1e3, 3), "GCUPS": round(cells / k / 1e9, 3), "result": v,
                  "oracle": gold[gname], "rel_err_vs_oracle": abs(v - gold[gname]) / gold[gname],
-                 "ops_per_cell": ops,
-                 "roofline_frac": round(ops * cells / k / 1e12 / VALU_PEAK_TOPS, 4)}
-        if peaks:
-            rate = peaks["f64_add_min_T_lane_op_s"] if prec == "f64" else peaks["f32_add_min_T_lane_op_s"]
-            entry["frac_of_measured_peak"] = round(ops * cells / k / 1e12 / rate, 4)
+                 "roofline": roofline_of(mix, cells / k / 1e9, peaks)}
         out[key] = entry
         del A, TA, B, TB, ws
     log(f"pair 3d n=1e5: {out}")
@@ -328,7 +368,7 @@ def batch_checks(torch, tw, col, X, T, D, dev, samples=256):
     return out
 
 
-def paper_shapes(torch, tw, synth, dev):
+def paper_shapes(torch, tw, synth, dev, peaks=None):
     """1-D FP64 workloads of the paper's tables: single pairs of random walks
     N = 2^10 .. 2^20 (the C1 generator, seeds 0/1, t = 0..N-1, nu = 1e-3,
     lambda = 1, L1) next to the paper's device-resident timings (table "Raw
@@ -353,8 +393,7 @@ def paper_shapes(torch, tw, synth, dev):
                                        "speedup_vs_paper_gpu": round(PAPER_CUTWED_DEV_S[N] / k, 1)}
     # (N = 2^20 also gives the 1-D FP64 roofline fraction)
     k20 = out["single_pairs"][str(1 << 20)]["ms"] / 1e3
-    out["single_pairs_2^20_roofline_frac"] = round(OPS_PER_CELL_1D_L1_F64 * float(1 << 40) / k20 / 1e12
-                                                   / VALU_PEAK_TOPS, 4)
+    out["single_pairs_2^20_roofline"] = roofline_of(MIX_1D_L1_F64, float(1 << 40) / k20 / 1e9, peaks)
     for count, length, paper_s, name in ((600, 60, 1.0, "600x60"), (10, 100_000, 147.0, "10x100k")):
         col = synth.paper_shaped_collection(count, length)
         X, T = f64(col.X), f64(col.T)
@@ -442,7 +481,6 @@ def main():
     ms_step = wall / args.steps * 1e3
     gcups = cells * args.steps / wall / 1e9
     kern_s = float(np.mean(per))
-    achieved = OPS_PER_CELL_8D_L2_ACC64 * cells / kern_s / 1e12
     log(f"headline: {ms_step:.1f} ms/step, {gcups:.1f} GCUPS, value {value!r}")
 
     result = {
@@ -461,19 +499,12 @@ def main():
         "config": {"workload": f"single pair, 8-D random walks n=m={n}, regular timestamps, nu=1e-3, "
                                f"lambda=1, L2, FP32 costs + FP64 accumulators",
                    "cells_per_step": cells, "result": value},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                     "unit": "T VALU lane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": counter_traffic(n, args.strip_k),
-                     "kernel": "wavefront_kernel<float,double,8,L2,K>",
-                     "ops_per_cell": OPS_PER_CELL_8D_L2_ACC64, "kernel_avg_s": kern_s},
+        "roofline": roofline_of(MIX_8D_L2_ACC64, cells / kern_s / 1e9, peaks),
     }
-
+    result["roofline"].update({"traffic": counter_traffic(n, args.strip_k),
+                               "kernel": "wavefront_kernel<float,double,8,L2,K>", "kernel_avg_s": kern_s})
     if peaks:
         result["measured_peaks"] = peaks
-        # the sweep issues FP32 cost and FP64 accumulator operations; the
-        # lower of the two measured add+min rates is its ceiling
-        mp = min(peaks["f32_add_min_T_lane_op_s"], peaks["f64_add_min_T_lane_op_s"])
-        result["roofline"]["frac_of_measured_peak"] = round(achieved / mp, 4)
 
     # ---- the same pair in FP64 on the GPU (inputs: the FP32 values widened),
     # and the mixed-precision result's error against it
@@ -521,11 +552,8 @@ def main():
                         "lambda=1, L1; symmetric matrix (upper triangle swept)",
             "cells_per_step": bcells, "ms_per_step": round(bwall / max(args.steps, 3) * 1e3, 3),
             "GCUPS": round(bcells / bk / 1e9, 3),
-            "roofline_frac": round(OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / VALU_PEAK_TOPS, 4),
+            "roofline": roofline_of(MIX_1D_L1_F32, bcells / bk / 1e9, peaks),
         }
-        if peaks:
-            result["batched_all_pairs"]["frac_of_measured_peak"] = round(
-                OPS_PER_CELL_1D_L1_F32 * bcells / bk / 1e12 / peaks["f32_add_min_T_lane_op_s"], 4)
         result["batched_all_pairs"].update(batch_checks(torch, tw, col, X, T, D, dev))
         # the same batch as a plan, before and after the autotuner
         plan = tw.BatchPlan(col.off, precision="f32", device=dev)
@@ -633,6 +661,7 @@ def main():
             "ms_per_query_collection_staged_once": round(float(np.mean(pper)) * 1e3, 4),
             "GCUPS_collection_staged_once": round(rcells / float(np.mean(pper)) / 1e9, 3),
             "paper_gpu_s": 0.20,
+            "roofline_staged_once": roofline_of(MIX_28D_L2_F64, rcells / float(np.mean(pper)) / 1e9, peaks),
         }
         log(f"rn query: {result['rn_query']}")
         if args.rn_all:
@@ -656,10 +685,10 @@ def main():
     # ---- the paper's own shapes (1-D FP64): single pairs N = 2^10 .. 2^20,
     # 600 x 60 and 10 x 100k all-pairs
     if not args.no_paper:
-        result["paper_shapes"] = paper_shapes(torch, tw, synth, dev)
+        result["paper_shapes"] = paper_shapes(torch, tw, synth, dev, peaks)
 
     # ---- learned k-NN: train, index, query; recall against exhaustive TWED
-    if args.knn:
+    if not args.no_knn:
         result["knn"] = knn_bench(args, torch, tw, synth, dev, time_steps)
 
     # ---- CPU oracle on a bounded sample (prefix of the headline pair)

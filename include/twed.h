@@ -391,10 +391,12 @@ int64_t twed_batch_max_short_length(int32_t dim);
  * of 64 lanes (a multiple of 4, at most 2^24) each run `iters` iterations
  * of eight independent chains of: kind 0 an FP32 fused multiply-add; 1 an
  * FP32 add then minimum; 2 an FP64 fused multiply-add; 3 an FP64 add then
- * minimum.  sink: device, waves*64 floats (kinds 0, 1) or doubles (2, 3),
- * overwritten.  *lane_ops (host, may be NULL) receives the lane operations
- * issued (an add and a minimum count as two).  Errors: TWED_ERR_INVALID for
- * an unknown kind, iters < 1, a bad wave count or a NULL sink. */
+ * minimum; 4 an FP32 square root; 5 an FP32 add; 6 an FP64 add; 7 an FP32
+ * three-way minimum.  sink: device, waves*64 doubles (kinds 2, 3, 6) or
+ * floats (the others), overwritten.  *lane_ops (host, may be NULL) receives
+ * the lane operations issued (an add and a minimum count as two, a
+ * three-way minimum as one).  Errors: TWED_ERR_INVALID for an unknown kind,
+ * iters < 1, a bad wave count or a NULL sink. */
 twed_status twed_probe_valu(int32_t kind, int64_t waves, int64_t iters, void *sink, double *lane_ops,
                             hipStream_t stream);
 

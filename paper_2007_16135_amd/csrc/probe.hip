@@ -17,7 +17,10 @@ namespace {
 constexpr int kChains = 8;
 constexpr int kProbeThreads = 256;
 
-template <typename T, bool FMA>
+// Operation of one probe chain step.
+enum ProbeOp : int { kFma = 0, kAddMin = 1, kSqrt = 2, kAdd = 3, kMin3 = 4 };
+
+template <typename T, int OP>
 __global__ __launch_bounds__(kProbeThreads) void valu_probe_kernel(int64_t iters, T seed, T *__restrict__ sink)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -31,14 +34,22 @@ __global__ __launch_bounds__(kProbeThreads) void valu_probe_kernel(int64_t iters
     for (int64_t i = 0; i < iters; ++i) {
 #pragma unroll
         for (int r = 0; r < kChains; ++r) {
-            if constexpr (FMA && sizeof(T) == 4) {
+            if constexpr (OP == kFma && sizeof(T) == 4) {
                 a[r] = __builtin_fmaf(a[r], b, c[r]);
-            } else if constexpr (FMA) {
+            } else if constexpr (OP == kFma) {
                 a[r] = __builtin_fma(a[r], b, c[r]);
-            } else if constexpr (sizeof(T) == 4) {
+            } else if constexpr (OP == kAddMin && sizeof(T) == 4) {
                 a[r] = __builtin_fminf(a[r] + b, c[r]);
-            } else {
+            } else if constexpr (OP == kAddMin) {
                 a[r] = __builtin_fmin(a[r] + b, c[r]);
+            } else if constexpr (OP == kSqrt) {
+                static_assert(sizeof(T) == 4, "the square-root probe is FP32 (the sweep's cost type)");
+                a[r] = __builtin_amdgcn_sqrtf(a[r]);
+            } else if constexpr (OP == kAdd) {
+                a[r] = a[r] + b;
+            } else {
+                static_assert(sizeof(T) == 4, "three-way minimum probe is FP32");
+                a[r] = __builtin_fminf(__builtin_fminf(a[r], b), c[r]);
             }
         }
     }
@@ -58,7 +69,7 @@ extern "C" twed_status twed_probe_valu(int32_t kind, int64_t waves, int64_t iter
                                        hipStream_t stream)
 {
     last_error().clear();
-    if (kind < 0 || kind > 3) return fail(TWED_ERR_INVALID, "kind must be 0..3");
+    if (kind < 0 || kind > 7) return fail(TWED_ERR_INVALID, "kind must be 0..7");
     if (waves < 4 || waves % 4 != 0 || waves > (int64_t(1) << 24)) return fail(TWED_ERR_INVALID, "waves must be a multiple of 4 in [4, 2^24]");
     if (iters < 1) return fail(TWED_ERR_INVALID, "iters must be >= 1");
     if (!sink) return fail(TWED_ERR_INVALID, "sink is NULL");
@@ -66,20 +77,36 @@ extern "C" twed_status twed_probe_valu(int32_t kind, int64_t waves, int64_t iter
     const double per_iter = kind == 1 || kind == 3 ? 2.0 : 1.0;  // add + min count as two operations
     switch (kind) {
     case 0:
-        hipLaunchKernelGGL((valu_probe_kernel<float, true>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+        hipLaunchKernelGGL((valu_probe_kernel<float, kFma>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
                            0.999f, (float *)sink);
         break;
     case 1:
-        hipLaunchKernelGGL((valu_probe_kernel<float, false>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+        hipLaunchKernelGGL((valu_probe_kernel<float, kAddMin>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
                            0.999f, (float *)sink);
         break;
     case 2:
-        hipLaunchKernelGGL((valu_probe_kernel<double, true>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+        hipLaunchKernelGGL((valu_probe_kernel<double, kFma>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+                           0.999, (double *)sink);
+        break;
+    case 3:
+        hipLaunchKernelGGL((valu_probe_kernel<double, kAddMin>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+                           0.999, (double *)sink);
+        break;
+    case 4:
+        hipLaunchKernelGGL((valu_probe_kernel<float, kSqrt>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+                           0.999f, (float *)sink);
+        break;
+    case 5:
+        hipLaunchKernelGGL((valu_probe_kernel<float, kAdd>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+                           0.999f, (float *)sink);
+        break;
+    case 6:
+        hipLaunchKernelGGL((valu_probe_kernel<double, kAdd>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
                            0.999, (double *)sink);
         break;
     default:
-        hipLaunchKernelGGL((valu_probe_kernel<double, false>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
-                           0.999, (double *)sink);
+        hipLaunchKernelGGL((valu_probe_kernel<float, kMin3>), dim3(blocks), dim3(kProbeThreads), 0, stream, iters,
+                           0.999f, (float *)sink);
         break;
     }
     const hipError_t e = hipGetLastError();

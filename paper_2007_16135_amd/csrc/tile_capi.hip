@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 
 using namespace twed;
 using namespace twed::capi;
@@ -46,8 +47,8 @@ struct Sweep {
 };
 
 // The widest strip whose kernel keeps to registers and still leaves about
-// 1.5 strips per SIMD, in the widest non-spilling group that leaves about one
-// group per CU (the rules of the pair sweep).
+// three strips for every four SIMDs (the rule of the pair sweep), in the
+// widest non-spilling group that leaves work for half the CUs.
 // The recurrence a sweep runs: kRecTwed, or a sibling (kRecDtw, kRecEdit,
 // kRecIndel; see twed_device.h), whose kernels exist for K in {1, 8} and G
 // in {1, 8} only.
@@ -73,7 +74,7 @@ Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &
     } else if (strip_k > 0) {
         K = strip_k;
     } else {
-        const int64_t want = (int64_t)simds() * 3 / 2;
+        const int64_t want = (int64_t)simds() * 3 / 4;
         for (int k : {8, 4, 2}) {
             if (sib && k != 8) continue;
             const int64_t strips = (nB + 64 * k - 1) / (64 * k);
@@ -97,6 +98,12 @@ Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &
             G = g;
             break;
         }
+    }
+    // TWED_WAVEFRONT_GROUP (1, 4 or 8) overrides the group of plain TWED
+    // tile sweeps for tuning runs
+    if (const char *env = std::getenv("TWED_WAVEFRONT_GROUP")) {
+        const int g = std::atoi(env);
+        if (!sib && !dirs && (g == 1 || g == 4 || g == 8) && sweep_scratch(rec, dirs, prec, cp, K, g) == 0) G = g;
     }
     return Sweep{K, G};
 }

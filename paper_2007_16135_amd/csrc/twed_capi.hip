@@ -65,13 +65,17 @@ int device_simds()
 }
 
 // Columns per lane of the wavefront sweep: the widest strip that still
-// leaves about 1.5 strips per SIMD, so the pipeline covers the machine, and
-// whose kernel keeps everything in registers (wide strips of high-dimensional
-// or general-Lp sweeps would spill).
+// leaves about three strips for every four SIMDs, and whose kernel keeps
+// everything in registers (wide strips of high-dimensional or general-Lp
+// sweeps would spill).  Narrow strips fill more SIMDs but lengthen the
+// pipeline (each strip starts 64 + 16 steps after the one before it) and
+// pay the per-step work for fewer cells: on the 3-D n = 1e5 pair, strips of
+// two columns (782 strips) sweep 1.36x faster in FP64 than strips of one
+// (1,563 strips, two waves on some SIMDs).
 int choose_k(const twed_params *prm, int64_t nB, Prec prec, const CostParams &cp)
 {
     if (prm->strip_k > 0) return prm->strip_k;
-    const int64_t want = (int64_t)device_simds() * 3 / 2;
+    const int64_t want = (int64_t)device_simds() * 3 / 4;
     for (int k : {8, 4, 2}) {
         const int64_t strips = (nB + 64 * k - 1) / (64 * k);
         if (strips >= want && wavefront_scratch_bytes(prec, cp, k, 1) == 0) return k;
@@ -216,17 +220,18 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     w.out = out;
     w.dump = dump;
     // Strips per workgroup: in-group handoffs go through LDS, one in G
-    // through global memory.  The widest group that still leaves about one
-    // group per CU and whose kernel keeps to registers (eight waves put two
-    // on each SIMD, which halves the registers a lane may hold: too few for
-    // the widest high-dimensional strips); cell dumps use single-wave groups.
+    // through global memory.  The widest group that still leaves about
+    // three groups for every four CUs and whose kernel keeps to registers
+    // (eight waves put two on each SIMD, which halves the registers a lane
+    // may hold: too few for the widest high-dimensional strips); cell dumps
+    // use single-wave groups.
     // TWED_WAVEFRONT_GROUP
     // (1, 4 or 8) and TWED_WAVEFRONT_SUB (in-group handoff rows: 8, 16 or 32)
     // override the choices for tuning runs.
     const int64_t cus = std::max(1, device_simds() / 4);
     w.group = 1;
     for (int G : {8, 4})
-        if (w.nStrips * 10 >= (int64_t)G * cus * 9 && wavefront_scratch_bytes(prec, cp, K, G) == 0) {
+        if (w.nStrips * 4 >= (int64_t)G * cus * 3 && wavefront_scratch_bytes(prec, cp, K, G) == 0) {
             w.group = G;
             break;
         }

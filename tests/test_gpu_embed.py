@@ -344,15 +344,18 @@ def test_knn_pruned_candidates():
 
 
 def test_training_lowers_loss_and_helps_recall():
-    # what the trained network gains: at the same candidate budget it finds
-    # more of the exact neighbours than the untrained one, and the exact
-    # re-rank finds more than the network's own ranking
+    # What the trained network gains, at the 200-candidate budget of the
+    # k-NN query: it finds clearly more of the exact neighbours than the
+    # untrained network (measured gains on this seed and collection: +0.10
+    # to +0.18), and the exact re-rank finds far more than the network's own
+    # ranking (+0.4).  64 queries against 1,500 database series; recall is
+    # taken against the FP64 oracle's exact neighbours.
     db, DB, TDB = collection(1500, 3)
-    qc, Q, TQ = collection(24, 4)
+    qc, Q, TQ = collection(64, 4)
     dbc = knn.Collection(dev(DB), dev(TDB), db.off)
     tr = knn.Trainer(dbc, NU, LAM, seed=0, batch_series=128, pairs_per_step=1024, n_anchors=512)
     first = float(tr.step().item())
-    secs = tr.train(399)
+    secs = tr.train(999)
     last = float(np.mean([float(tr.step().item()) for _ in range(5)]))
     say(f"training: loss {first:.4f} -> {last:.4f} in {secs:.1f} s (mining {tr.mine_s:.1f} s), "
         f"{tr.pairs_seen} pairs")
@@ -363,15 +366,14 @@ def test_training_lowers_loss_and_helps_recall():
     rec = {}
     for name, vec in (("trained", tr.params.cpu().numpy()), ("untrained", knn.init_params(0))):
         ix = index_for(DB, TDB, db.off, vec)
-        for c in (60, 150):
-            ids, _ = ix.query(dev(Q), dev(TQ), qc.off, k=10, n_cand=c)
-            rec[f"{name}@{c}"] = knn.recall_at(ids.cpu().numpy(), truth)
+        ids, _ = ix.query(dev(Q), dev(TQ), qc.off, k=10, n_cand=200)
+        rec[f"{name}@200"] = knn.recall_at(ids.cpu().numpy(), truth)
         ids_net, _ = ix.query(dev(Q), dev(TQ), qc.off, k=10, n_cand=10)
         rec[name + "_network_only"] = knn.recall_at(ids_net.cpu().numpy(), truth)
         ix.close()
     say(f"recall@10: {rec}")
-    assert rec["trained@150"] >= rec["untrained@150"]
-    assert rec["trained@150"] > rec["trained_network_only"]
+    assert rec["trained@200"] >= rec["untrained@200"] + 0.05
+    assert rec["trained@200"] >= rec["trained_network_only"] + 0.25
 
 
 def test_knn_long_series_exhaustive():
