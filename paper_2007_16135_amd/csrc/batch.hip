@@ -97,33 +97,35 @@ __device__ __forceinline__ AT sweep_pair(const CT *__restrict__ rowsA, int nA, c
     return lane_value(res, lstar);
 }
 
-template <typename CT, typename AT, int DIMT, int PM, int K>
+template <typename CT, typename AT, int DIMT, int PM, int K, int KHI>
 __device__ __forceinline__ AT sweep_dispatch(int k, const CT *rowsA, int nA, const CT *rowsB, int nB,
                                              const CostArgs<CT> &ca)
 {
-    if constexpr (K > kmax_of<DIMT>()) {
+    if constexpr (K > kmax_of<DIMT>() || K > KHI) {
         return AT(0);
     } else {
         if (k == K) return sweep_pair<CT, AT, DIMT, PM, K>(rowsA, nA, rowsB, nB, ca);
-        return sweep_dispatch<CT, AT, DIMT, PM, K + 1>(k, rowsA, nA, rowsB, nB, ca);
+        return sweep_dispatch<CT, AT, DIMT, PM, K + 1, KHI>(k, rowsA, nA, rowsB, nB, ca);
     }
 }
 
-template <typename CT, typename AT, int DIMT, int PM>
+// Items item0 .. nItems-1; pairs of KLO..KHI columns per lane (clipped to
+// what the sample width allows) are swept, the others left to other launches.
+template <typename CT, typename AT, int DIMT, int PM, int KLO, int KHI>
 __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX, const CT *__restrict__ rowsY,
                                                    const int64_t *__restrict__ offX,
                                                    const int64_t *__restrict__ offY,
                                                    const int32_t *__restrict__ order,
                                                    const int64_t *__restrict__ pairs, int64_t nX, int64_t nY,
-                                                   int64_t nItems, int mode, CostArgs<CT> ca, AT *D,
+                                                   int64_t item0, int64_t nItems, int mode, CostArgs<CT> ca, AT *D,
                                                    uint32_t *ticket, int chunk)
 {
     constexpr int S = Row<CT, DIMT>::kStride;
-    constexpr int KMAX = kmax_of<DIMT>();
+    constexpr int KMAX = kmax_of<DIMT>() < KHI ? kmax_of<DIMT>() : KHI;
     // A ticket is `chunk` consecutive items: for short pairs one atomic per
     // pair on a single counter would cost more than the pair itself.
     for (;;) {
-        const int64_t first = (int64_t)next_ticket(ticket) * chunk;
+        const int64_t first = item0 + (int64_t)next_ticket(ticket) * chunk;
         if (first >= nItems) break;
         const int64_t last = first + chunk < nItems ? first + chunk : nItems;
         for (int64_t item = first; item < last; ++item) {
@@ -162,10 +164,10 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
             const int nB = (int)(swap ? la : lb);
             const int k = (nB + kWave - 1) / kWave;
             // Pairs wider than one wave are swept by the single-pair path instead.
-            if (k <= KMAX) {
+            if (k >= KLO && k <= KMAX) {
                 // d is the same in every lane; every lane stores it (one
                 // transaction), so the loop body holds no lane-conditional branch.
-                const AT d = sweep_dispatch<CT, AT, DIMT, PM, 1>(k, rowsA, nA, rowsB, nB, ca);
+                const AT d = sweep_dispatch<CT, AT, DIMT, PM, KLO, KMAX>(k, rowsA, nA, rowsB, nB, ca);
                 if (mode == kSymmetric) {
                     D[a * nX + b] = d;
                     D[b * nX + a] = d;
@@ -265,24 +267,41 @@ __global__ __launch_bounds__(kWave) void batch_lane_kernel(const CT *__restrict_
     }
 }
 
-template <typename CT, typename AT, int DIMT, int PM>
-static int batch_occupancy()
+// Calls f<KLO, KHI>() with the batch_kernel range of a width class.  Samples
+// of more than one component have KMAX <= 8, so their three classes share
+// one kernel.
+template <typename CT, typename AT, int DIMT, int PM, typename F>
+static auto by_class(int cls, F &&f)
 {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<CT, AT, DIMT, PM>, kWave, 0) !=
-        hipSuccess)
-        return 0;
-    return blocks;
+    if constexpr (kmax_of<DIMT>() > kBatchNarrowMax) {
+        if (cls == kBatchNarrow) return f.template operator()<1, kBatchNarrowMax>();
+        if (cls == kBatchWide) return f.template operator()<kBatchNarrowMax + 1, kmax_of<DIMT>()>();
+    }
+    return f.template operator()<1, kmax_of<DIMT>()>();
+}
+
+template <typename CT, typename AT, int DIMT, int PM>
+static int batch_occupancy(int cls)
+{
+    return by_class<CT, AT, DIMT, PM>(cls, [&]<int KLO, int KHI>() -> int {
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<CT, AT, DIMT, PM, KLO, KHI>, kWave,
+                                                         0) != hipSuccess)
+            return 0;
+        return blocks;
+    });
 }
 
 hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hipStream_t st)
 {
     return by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
-        hipLaunchKernelGGL((batch_kernel<CT, AT, DIMT, PM>), dim3(a.grid), dim3(kWave), 0, st,
-                           (const CT *)a.rowsX, (const CT *)a.rowsY, a.offX, a.offY, a.order, a.pairs, a.nX,
-                           a.nY, a.nItems, a.mode, CostArgs<CT>::make(cp), (AT *)a.D, a.ticket,
-                           a.chunk > 1 ? a.chunk : 1);
-        return hipGetLastError();
+        return by_class<CT, AT, DIMT, PM>(a.kclass, [&]<int KLO, int KHI>() -> hipError_t {
+            hipLaunchKernelGGL((batch_kernel<CT, AT, DIMT, PM, KLO, KHI>), dim3(a.grid), dim3(kWave), 0, st,
+                               (const CT *)a.rowsX, (const CT *)a.rowsY, a.offX, a.offY, a.order, a.pairs, a.nX,
+                               a.nY, a.item0, a.nItems, a.mode, CostArgs<CT>::make(cp), (AT *)a.D, a.ticket,
+                               a.chunk > 1 ? a.chunk : 1);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -298,11 +317,11 @@ hipError_t launch_batch_lane(Prec prec, const CostParams &cp, const void *rowsQ,
     });
 }
 
-int batch_max_workers(Prec prec, const CostParams &cp)
+int batch_max_workers(Prec prec, const CostParams &cp, int kclass)
 {
     int per_cu = 0;
     hipError_t e = by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
-        per_cu = batch_occupancy<CT, AT, DIMT, PM>();
+        per_cu = batch_occupancy<CT, AT, DIMT, PM>(kclass);
         return hipSuccess;
     });
     if (e != hipSuccess || per_cu <= 0) return 0;

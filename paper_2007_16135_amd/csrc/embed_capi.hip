@@ -589,7 +589,11 @@ twed_status twed_knn(const twed_knn_index *ix, const void *Q, const void *TQ, co
     b.mode = kPairList;
     b.D = L.dist;
     b.ticket = L.ticket;
-    const int workers = batch_max_workers(kF32, cp);
+    // pairs of at most 8 columns per lane (both series of at most 512
+    // samples) run the narrow kernel, which fits more waves per SIMD
+    const int64_t k_need = (std::min(maxQ, ix->maxlen) + kWaveLanes - 1) / kWaveLanes;
+    b.kclass = k_need <= kBatchNarrowMax ? kBatchNarrow : kBatchAll;
+    const int workers = batch_max_workers(kF32, cp, b.kclass);
     if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
     b.grid = (int)std::min<int64_t>(nItems, workers);
     TRY(launch_batch(kF32, cp, b, st), "re-rank launch");

@@ -368,7 +368,7 @@ BatchLayout batch_layout(char *base, int64_t totX, int64_t nX, int64_t maxX, int
     L.offX = c.take((size_t)(nX + 1) * 8);
     L.offY = symmetric ? L.offX : c.take((size_t)(nY + 1) * 8);
     L.order = c.take((size_t)nX * 4);
-    L.zero = c.take(4);  // batch ticket
+    L.zero = c.take(8);  // batch tickets: one per launch of the sweep
     // single-pair sweep state for pairs too long for one wave
     const int64_t maxlen = std::max(maxX, maxY);
     const int64_t kshort = twed_batch_max_short_length(prm->dim);
@@ -539,7 +539,7 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
     twed_status s = TWED_OK;
     hipError_t e;
     e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, totX + nX, L.rowsX,
-                     (uint32_t *)L.zero, 1, st);
+                     (uint32_t *)L.zero, 2, st);
     if (e != hipSuccess) return fail_hip(e, "staging launch");
     if (!sym && Y) {
         e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, totY + nY, L.rowsY, nullptr, 0,
@@ -564,12 +564,31 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
     b.D = Dk;
     b.ticket = (uint32_t *)L.zero;
     if (b.nItems > 0xffffffffLL) return fail(TWED_ERR_UNSUPPORTED, "more than 2^32 - 1 pairs in one call");
-    int workers = batch_max_workers(prec, cp);
-    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
-    if (P.cfg.waves_per_cu > 0) {
-        const int cus = std::max(1, device_simds() / 4);
-        workers = std::min(workers, P.cfg.waves_per_cu * cus);
+    // Width classes: a pair's K (columns per lane) is ceil(shorter length /
+    // 64).  Only pairs of K <= 8 need no more than the narrow kernel; in the
+    // symmetric case the longest-first order puts every pair of K > 8 (both
+    // series longer than 512 samples) before the others, so the items split
+    // into a wide launch and a narrow one.
+    const int kmax = batch_kmax(cp.dimt);
+    const int64_t k_need = (std::min(maxX, maxY) + kWaveLanes - 1) / kWaveLanes;
+    int64_t split = 0;  // symmetric: items [0, split) hold the pairs of K > 8
+    int kclass = kBatchAll;
+    if (k_need <= kBatchNarrowMax || kmax <= kBatchNarrowMax) {
+        kclass = kBatchNarrow;
+    } else if (sym) {
+        int64_t J = 0;  // first series (in the order) of at most 512 samples
+        while (J < nX && offX[P.order[J] + 1] - offX[P.order[J]] > (int64_t)kBatchNarrowMax * kWaveLanes) ++J;
+        split = J * (J - 1) / 2;
+        kclass = -1;  // two launches
     }
+    const int cus = std::max(1, device_simds() / 4);
+    auto workers_of = [&](int cls) {
+        int wk = batch_max_workers(prec, cp, cls);
+        if (P.cfg.waves_per_cu > 0) wk = std::min(wk, P.cfg.waves_per_cu * cus);
+        return wk;
+    };
+    int workers = workers_of(kclass < 0 ? kBatchNarrow : kclass);
+    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
     if (sym) {
         e = launch_batch_diag_zero(prec, Dk, nX, st);
         if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
@@ -590,9 +609,34 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
             chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, b.nItems / (4 * (int64_t)workers)));
         }
         b.chunk = (int)chunk;
-        b.grid = (int)std::min<int64_t>((b.nItems + chunk - 1) / chunk, workers);
-        e = launch_batch(prec, cp, b, st);
-        if (e != hipSuccess) return fail_hip(e, "batch launch");
+        if (kclass >= 0) {
+            b.kclass = kclass;
+            b.grid = (int)std::min<int64_t>((b.nItems + chunk - 1) / chunk, workers);
+            e = launch_batch(prec, cp, b, st);
+            if (e != hipSuccess) return fail_hip(e, "batch launch");
+        } else {
+            // the wide pairs first (longest first), then the narrow ones on
+            // the second ticket
+            BatchArgs w = b;
+            w.kclass = kBatchWide;
+            w.nItems = split;
+            const int wide_workers = workers_of(kBatchWide);
+            if (wide_workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+            w.grid = (int)std::min<int64_t>((split + chunk - 1) / chunk, wide_workers);
+            if (split > 0) {
+                e = launch_batch(prec, cp, w, st);
+                if (e != hipSuccess) return fail_hip(e, "batch launch");
+            }
+            BatchArgs nrw = b;
+            nrw.kclass = kBatchNarrow;
+            nrw.item0 = split;
+            nrw.ticket = (uint32_t *)L.zero + 1;
+            nrw.grid = (int)std::min<int64_t>((b.nItems - split + chunk - 1) / chunk, workers);
+            if (b.nItems > split) {
+                e = launch_batch(prec, cp, nrw, st);
+                if (e != hipSuccess) return fail_hip(e, "batch launch");
+            }
+        }
     }
 
     // listed pairs whose shorter series exceeds one wave (the batch kernel

@@ -166,7 +166,20 @@ struct BatchArgs {
     uint32_t *ticket;            // one word, zero
     int grid;
     int chunk;                   // consecutive items per ticket (0 or 1: one)
+    int64_t item0;               // first item of this launch (items item0 .. nItems-1)
+    int kclass;                  // kernel of the pair widths swept (BatchClass)
 };
+// Pair widths (columns per lane K) a batch kernel sweeps; pairs outside its
+// range are left to another launch.  One kernel for every width holds the
+// registers of the widest, which limits it to two waves per SIMD; narrower
+// kernels fit more.
+enum BatchClass : int {
+    kBatchAll = 0,     // K = 1 .. KMAX
+    kBatchNarrow = 1,  // K = 1 .. min(8, KMAX)
+    kBatchWide = 2     // K = 9 .. KMAX (one-component samples only)
+};
+constexpr int kBatchNarrowMax = 8;
+constexpr int kWaveLanes = 64;  // lanes of a wave (gfx950 runs wave64)
 hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hipStream_t st);
 int batch_kmax(int dimt);
 // One query of at most kLaneMaxQuery samples (staged rows rowsQ) against nY
@@ -174,7 +187,7 @@ int batch_kmax(int dimt);
 constexpr int kLaneMaxQuery = 32;
 hipError_t launch_batch_lane(Prec prec, const CostParams &cp, const void *rowsQ, int nQ, const void *rowsY,
                             const int64_t *offY, int64_t nY, void *D, uint32_t *ticket, int grid, hipStream_t st);
-int batch_max_workers(Prec prec, const CostParams &cp);
+int batch_max_workers(Prec prec, const CostParams &cp, int kclass = kBatchAll);
 hipError_t launch_batch_diag_zero(Prec prec, void *D, int64_t n, hipStream_t st);
 // dst[0] = src[0] on the device (accumulator type of prec).
 hipError_t launch_copy_one(Prec prec, const void *src, void *dst, hipStream_t st);

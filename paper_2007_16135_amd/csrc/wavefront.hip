@@ -15,12 +15,14 @@
 //  * The left and up-left operands of a lane's first column come from lane
 //    l-1 through one DPP wave shift per step.
 //  * Lane 0 of strip s takes them from the right-boundary column of strip
-//    s-1 (DP and DP+e per row).  That strip collects its lane 63 outputs in
-//    a register (one DPP shift per step), writes them to one of two global
-//    slots every kChunk rows and publishes them with a release flag; the
-//    consumer polls the flag and acquires before loading kChunk rows at once.
-//    Two slots suffice: strip s+2 can only write row r after strip s+1 has
-//    published row r, which it does after reading it.
+//    s-1 (DP and DP+e per row), one broadcast LDS read per step.  Lane 63
+//    of strip s-1 writes that column to LDS as it produces it, one row per
+//    step: into the ring the next wave of the workgroup reads, or into a
+//    staging ring from which whole windows of rows go to one of two global
+//    slots, published with a release flag; the consumer polls the flag and
+//    acquires before copying the window into its own LDS.  Two slots
+//    suffice: strip s+2 can only write row r after strip s+1 has published
+//    row r, which it does after reading it.
 //  * Waves take strips from an atomic ticket, so the wave that strip s waits
 //    for has always started: no co-residency assumption, no deadlock.
 //

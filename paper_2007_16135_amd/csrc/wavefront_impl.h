@@ -28,30 +28,12 @@ constexpr int kRing = 128;
 template <typename AT, int G>
 struct GroupShared {
     Pair2<AT> ring[G > 1 ? G - 1 : 1][kRing + 1];  // boundary of wave w, read by wave w+1
+    Pair2<AT> in_stage[kWindow];                   // wave 0's left boundary, one global window
+    Pair2<AT> out_stage[kRing + 1];                // wave G-1's right boundary before it goes out
     uint32_t prod[G];                              // rows of that boundary published
     uint32_t cons[G];                              // rows of wave w's left boundary consumed
     uint32_t ticket[G];                            // ticket value seen by each wave (wave 0's is the claim)
 };
-
-// DPP control "wave_shl:1": lane i receives lane i+1; lane 63 keeps `old`.
-constexpr int kDppWaveShl1 = 0x130;
-
-__device__ __forceinline__ float collect(float v_lane63, float col)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        __builtin_bit_cast(int, v_lane63), __builtin_bit_cast(int, col), kDppWaveShl1, 0xf, 0xf, false));
-}
-
-__device__ __forceinline__ double collect(double v_lane63, double col)
-{
-    uint64_t u = __builtin_bit_cast(uint64_t, col);
-    uint64_t o = __builtin_bit_cast(uint64_t, v_lane63);
-    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u,
-                                                        kDppWaveShl1, 0xf, 0xf, false);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
-                                                        kDppWaveShl1, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
 
 __device__ __forceinline__ uint32_t load_lds_progress(const uint32_t *p)
 {
@@ -150,8 +132,9 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     constexpr int W = kWave * K;
     const int lane = threadIdx.x & (kWave - 1);
     const AT INF = pinf<AT>();
-    const CT *rowsA_lane = rowsA - (ptrdiff_t)lane * S;  // row t of this pointer = row t - lane of A
-
+    // Row t - lane of A, the row lane `lane` works on at step t: a pointer
+    // that advances by one row per step (a 64-bit add, no multiply).
+    const CT *row_ptr = rowsA - (ptrdiff_t)lane * S;
     // ---- columns of this lane
     const int c0 = 1 + s * W + lane * K;
     Lane<CT, AT, DIMT, K> L;
@@ -208,28 +191,38 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     // Rows of A are loaded kAhead steps before their use: one step of 64*K
     // columns hides the load behind K cells of work, which is enough for
     // wide strips; narrow strips of small samples keep a ring of kAhead + 1
-    // rows (kAhead + 1 divides every sub-chunk of 8, 16 or 32 steps); one
-    // column per lane of 4-byte samples hides it behind 7 steps.
-    constexpr int kAhead = (K == 1 && sizeof(CT) == 4 && DIMT <= 8) ? 7 : (K <= 2 && DIMT <= 8) ? 3 : 1;
+    // rows (kAhead + 1 divides every sub-chunk of 8, 16 or 32 steps).  A
+    // deeper ring for one-column strips (7 rows ahead) pushed the tile
+    // kernels of eight-wave groups past 256 registers.
+    constexpr int kAhead = (K <= 2 && DIMT <= 8) ? 3 : 1;
     // lane 0 prefetches up to row nA + 63 + kAhead: inside the zero rows
     // that end every packed buffer
     static_assert(kWave - 1 + kAhead <= kRowPadTail, "row prefetch runs past the buffer padding");
     Row<CT, DIMT> cur, nxt;
     Row<CT, DIMT> ring[kAhead + 1];
     if constexpr (kAhead == 1) {
-        load_row<CT, DIMT>(rowsA_lane, 0, cur);
+        load_row<CT, DIMT>(row_ptr, 0, cur);
     } else {
 #pragma unroll
-        for (int k = 0; k < kAhead; ++k) load_row<CT, DIMT>(rowsA_lane, k, ring[k]);
+        for (int k = 0; k < kAhead; ++k) load_row<CT, DIMT>(row_ptr, k, ring[k]);
     }
-    // Left boundary of the current window of 64 steps: lane l holds row
-    // wb + 1 + l (DP in cdp, X in cx; two scalars, so that selecting a lane's
-    // new row stays in registers).
-    AT cdp = INF, cx = INF;
-    // Right-boundary collector: lane 63's (DP, X) of each step enters at
-    // lane 63 and moves down one lane per step, so after step t lane l holds
-    // row t - 126 + l of the boundary.
-    AT col_dp = INF, col_x = INF;
+    row_ptr += kAhead * S;  // row kAhead - lane: the first prefetch
+    // Lane 0's left operands of the next step come from one LDS read at a
+    // wave-uniform address (a broadcast: no cross-lane moves, no lane
+    // selection): from the ring of the previous wave of the group, or from
+    // in_stage, which holds one window of the global slot (or +inf: the pad
+    // column of the first strip).  Lane 63's output of every step -- the
+    // strip's right boundary -- is written by that lane alone to the ring of
+    // the next wave, or to out_stage when it leaves the group through global
+    // memory, from where whole windows are copied out.
+    const bool has_in = in_global || in_lds;
+    if (!has_in) sh.in_stage[lane] = Pair2<AT>{INF, INF};
+    // boundary row t + 1 sits at in_src[(t + in_add) & in_mask]: ring slot
+    // (t + 1) mod 128, or in_stage slot t - wb = t mod 64
+    const Pair2<AT> *const in_src = in_lds ? &sh.ring[w > 0 ? w - 1 : 0][0] : &sh.in_stage[0];
+    const int in_add = in_lds ? 1 : 0;
+    const int in_mask = in_lds ? kRing - 1 : kWindow - 1;
+    Pair2<AT> *const out_ring = out_lds ? &sh.ring[w < G - 1 ? w : 0][0] : &sh.out_stage[0];
 
     for (int t0 = 0; t0 < T; t0 += kSub) {
         const int q = (t0 >> sub_shift) & ((kWindow >> sub_shift) - 1);  // sub-chunk within the window
@@ -241,22 +234,22 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
                 wait_progress<false>(in_flag, need, err);
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
+            // rows t0 + 1 .. t0 + 64 of the boundary: lane l's row to slot l
             const int rr = t0 + 1 + lane < nA ? t0 + 1 + lane : nA;
-            const Pair2<AT> v = in_slot[rr];
-            cdp = v.dp;
-            cx = v.x;
+            sh.in_stage[lane] = in_slot[rr];
         }
         if (in_lds) {
+            // the rows this sub-chunk reads, t0 + 1 .. t0 + kSub, are in the ring
             const uint32_t need = (uint32_t)(t0 + kSub < nA ? t0 + kSub : nA);
             wait_progress<true>(&sh.prod[w - 1], need, err);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const int rr = wb + 1 + lane < nA ? wb + 1 + lane : nA;
-            const Pair2<AT> v = sh.ring[w > 0 ? w - 1 : 0][rr & (kRing - 1)];
-            const bool mine = (lane >> sub_shift) == q;  // lanes of this sub-chunk take their rows
-            cdp = mine ? v.dp : cdp;
-            cx = mine ? v.x : cx;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __hip_atomic_store(&sh.cons[w], need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (out_lds) {
+            // this sub-chunk writes rows up to t0 + steps - 64 into the ring,
+            // over the slots of rows up to 128 earlier: the next wave must
+            // have read those
+            const int last_w = t0 + steps - kWave;
+            if (last_w > kRing) wait_progress<true>(&sh.cons[w + 1], (uint32_t)(last_w - kRing), err);
         }
 
         // One step: sweep row t - lane with `use`, prefetch row t + kAhead -
@@ -266,7 +259,11 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
         // sub-chunks run without testing for them at every step.
         auto step = [&]<bool SP>(int i, Row<CT, DIMT> &use, Row<CT, DIMT> &fill) {
             const int t = t0 + i;
-            load_row<CT, DIMT>(rowsA_lane, t + kAhead, fill);
+            load_row<CT, DIMT>(row_ptr, 0, fill);  // row t + kAhead - lane
+            row_ptr += S;
+            // boundary row t + 1, which lane 0 meets at the next step (read
+            // before the cells so that its latency hides behind them)
+            const Pair2<AT> nb = in_src[(t + in_add) & in_mask];
 
             AT left = sh_l, xl;
             if constexpr (TILE) {
@@ -360,15 +357,13 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
                 out[0] = res;
             }
 
-            const bool has_in = in_global || in_lds;
-            const AT bl = has_in ? lane_value(cdp, t - wb) : INF;
-            const AT bx = has_in ? lane_value(cx, t - wb) : INF;
             sh_xo = sh_x;
-            sh_l = shift_in(left, bl);
-            sh_x = shift_in(xl, bx);
-            if (has_out) {
-                col_dp = collect(left, col_dp);
-                col_x = collect(xl, col_x);
+            sh_l = shift_in(left, nb.dp);
+            sh_x = shift_in(xl, nb.x);
+            if (has_out && lane == kWave - 1) {
+                // lane 63 holds row t - 63 of the strip's right boundary
+                const int r = t - (kWave - 1);
+                out_ring[(r >= 1 && r <= nA) ? (r & (kRing - 1)) : kRing] = Pair2<AT>{left, xl};
             }
         };
         auto run = [&]<bool SP>() {
@@ -422,25 +417,26 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
 
         const int tend = t0 + steps;        // steps done so far
         const int last = tend - kWave;      // last boundary row complete
+        if (in_lds) {
+            // rows up to tend have been read
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __hip_atomic_store(&sh.cons[w], (uint32_t)(tend < nA ? tend : nA), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         if (out_lds && last >= 1) {
-            // the ring holds rows last-kRing+1 .. last: the consumer must be
-            // past the rows being overwritten
-            if (last > kRing) wait_progress<true>(&sh.cons[w + 1], (uint32_t)(last - kRing), err);
-            int r = tend - 2 * kWave + 1 + lane;  // row held by this lane
-            const bool mine = lane >= kWave - steps && r >= 1 && r <= nA;
-            sh.ring[w < G - 1 ? w : 0][mine ? (r & (kRing - 1)) : kRing] = Pair2<AT>{col_dp, col_x};
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __hip_atomic_store(&sh.prod[w], (uint32_t)(last < nA ? last : nA), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         if (out_global && (q == (kWindow >> sub_shift) - 1 || tend >= T)) {
-            // the window's rows are in lanes kWave - (tend - wb) .. 63 (lanes
-            // without a row of this window write slot row 0, which no
-            // consumer reads: no lane-conditional branch)
+            // the window's rows, tend - 127 + lane for lanes kWave - (tend -
+            // wb) .. 63, from out_stage to the slot (lanes without a row of
+            // this window write slot row 0, which no consumer reads: no
+            // lane-conditional branch)
             const int ws = tend - wb;
             int r = tend - 2 * kWave + 1 + lane;
             r = (lane >= kWave - ws && r >= 1 && r <= nA) ? r : 0;
-            out_slot[r] = Pair2<AT>{col_dp, col_x};
+            out_slot[r] = sh.out_stage[r > 0 ? (r & (kRing - 1)) : kRing];
             if (last >= 1) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __hip_atomic_store(out_flag, (uint32_t)(last < nA ? last : nA), __ATOMIC_RELAXED,
@@ -453,7 +449,7 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
                 const int ws = tend - wb;
                 const int r = tend - 2 * kWave + 1 + lane;
                 const bool ok = lane >= kWave - ws && r >= 1 && r <= nA;
-                *(ok ? ck_col + r : io.dummy + lane) = Pair2<AT>{col_dp, col_x};
+                *(ok ? ck_col + r : io.dummy + lane) = out_ring[ok ? (r & (kRing - 1)) : kRing];
             }
         }
     }
@@ -478,7 +474,7 @@ __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restri
                                                              TileIO<AT> io)
 {
     __shared__ GroupShared<AT, G> sh;
-    const int w = (int)(threadIdx.x / kWave);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const CT beta = kShifted<AT> ? beta_ptr[0] : CT(0);
     const int nGroups = (nStrips + G - 1) / G;
     for (;;) {

@@ -115,6 +115,35 @@ def test_entries_equal_single_pair_call():
         assert float(v.item()) == D[i, j]
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_width_classes_bitwise(prec):
+    # A symmetric batch whose pairs fall in every width class: K <= 8 (the
+    # shorter series at most 512 samples), K = 9..16 (both longer than 512)
+    # and the single-pair sweep (both longer than 1024).  The wide pairs run
+    # in one launch, the narrow ones in another; every entry equals twed_pair
+    # bit for bit, and the pair-list and rectangular forms give the same.
+    rng = np.random.default_rng(61)
+    lens = [30, 200, 511, 512, 513, 700, 1000, 1024, 1025, 1500, 64, 577]
+    col = synth.pack([synth.walk(rng, L, 1) for L in lens], [synth.irregular_times(rng, L) for L in lens])
+    X, T = to_dev(col, prec)
+    say(f"width classes {prec}: {len(lens)} series")
+    D = tw.twed_batch(X, T, col.off, nu=1e-3, lam=1.0, p=1.0, precision=prec).cpu().numpy()
+    n = len(lens)
+    for i in range(n):
+        for j in range(i + 1, n):
+            a = slice(col.off[i], col.off[i + 1])
+            b = slice(col.off[j], col.off[j + 1])
+            v = tw.twed_pair(X[a], T[a], X[b], T[b], 1e-3, 1.0, 1.0, prec).item()
+            assert D[i, j] == v and D[j, i] == v, (lens[i], lens[j], D[i, j], v)
+    prs = np.array([(i, j) for i in range(n) for j in range(n) if i != j], dtype=np.int64)
+    Dp = tw.twed_batch(X, T, col.off, X, T, col.off, pairs=torch.as_tensor(prs, device="cuda"), nu=1e-3,
+                       lam=1.0, p=1.0, precision=prec).cpu().numpy()
+    assert np.array_equal(Dp, D[prs[:, 0], prs[:, 1]])
+    Dr = tw.twed_batch(X, T, col.off, X, T, col.off, nu=1e-3, lam=1.0, p=1.0, precision=prec).cpu().numpy()
+    off = ~np.eye(n, dtype=bool)
+    assert np.array_equal(Dr[off], D[off])
+
+
 def test_empty_pair_list_and_single_series():
     col = synth.batch_collection(1, 5, 50, seed=41)
     X, T = to_dev(col, "f32")
