@@ -189,9 +189,17 @@ __global__ __launch_bounds__(64) void batch_kernel(const CT *__restrict__ rowsX,
 // replaces that sweep for this shape because a wave per pair would spend
 // most of its lanes and steps filling and draining a 64-lane pipeline for a
 // few hundred cells.
-template <typename CT, typename AT, int DIMT, int PM>
+//
+// RAW: the series are read as the caller holds them (Y: dim components per
+// sample, TY: timestamps) instead of as staged rows, and each sample's
+// deletion cost is computed from the sample before it with the staging
+// kernel's arithmetic, so a collection queried once needs no staging pass
+// (a staged collection, reused by many queries, reads its rows instead).
+template <typename CT, typename AT, int DIMT, int PM, bool RAW>
 __global__ __launch_bounds__(kWave) void batch_lane_kernel(const CT *__restrict__ rowsQ, int nQ,
                                                            const CT *__restrict__ rowsY,
+                                                           const CT *__restrict__ Yraw,
+                                                           const CT *__restrict__ TYraw, int dim,
                                                            const int64_t *__restrict__ offY, int64_t nY,
                                                            CostArgs<CT> ca, AT *D, uint32_t *ticket)
 {
@@ -227,9 +235,25 @@ __global__ __launch_bounds__(kWave) void batch_lane_kernel(const CT *__restrict_
             xq[i] = INF;
         }
         AT res = INF;
+        CT px[DIMT], pt = CT(0);  // RAW: the sample before (the zero pad at j = 1)
+#pragma unroll
+        for (int k = 0; k < DIMT; ++k) px[k] = CT(0);
         for (int j = 1; j <= maxL; ++j) {
             Row<CT, DIMT> bj;
-            load_row<CT, DIMT>(rb, j <= lb ? j : lb, bj);
+            if constexpr (RAW) {
+                // columns past lb repeat sample lb (nothing reads them)
+                const int64_t r = yb + (j <= lb ? j : lb) - 1;
+#pragma unroll
+                for (int k = 0; k < DIMT; ++k) bj.x[k] = k < dim ? Yraw[r * dim + k] : CT(0);
+                bj.t = TYraw[r];
+                const CT d = point_dist<DIMT, PM, CT>(bj.x, px, ca.p, ca.invp);
+                bj.del = fma_(ca.nu, fabs_(bj.t - pt), d) + ca.lambda;
+#pragma unroll
+                for (int k = 0; k < DIMT; ++k) px[k] = bj.x[k];
+                pt = bj.t;
+            } else {
+                load_row<CT, DIMT>(rb, j <= lb ? j : lb, bj);
+            }
             const AT bdel = (AT)bj.del;
             AT above = INF;       // DP(i-1, j), starting at the pad row
             AT diag = xq[0];      // X(i-1, j-1)
@@ -306,13 +330,19 @@ hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hip
 }
 
 hipError_t launch_batch_lane(Prec prec, const CostParams &cp, const void *rowsQ, int nQ, const void *rowsY,
-                            const int64_t *offY, int64_t nY, void *D, uint32_t *ticket, int grid, hipStream_t st)
+                            const void *Yraw, const void *TYraw, const int64_t *offY, int64_t nY, void *D,
+                            uint32_t *ticket, int grid, hipStream_t st)
 {
     if (nQ < 1 || nQ > kLaneMaxQuery) return hipErrorInvalidValue;
     return by_prec(prec, cp.dimt, cp.pm, [&]<typename CT, typename AT, int DIMT, int PM>() -> hipError_t {
-        hipLaunchKernelGGL((batch_lane_kernel<CT, AT, DIMT, PM>), dim3(grid), dim3(kWave), 0, st,
-                           (const CT *)rowsQ, nQ, (const CT *)rowsY, offY, nY, CostArgs<CT>::make(cp), (AT *)D,
-                           ticket);
+        if (Yraw)
+            hipLaunchKernelGGL((batch_lane_kernel<CT, AT, DIMT, PM, true>), dim3(grid), dim3(kWave), 0, st,
+                               (const CT *)rowsQ, nQ, nullptr, (const CT *)Yraw, (const CT *)TYraw, cp.dim, offY,
+                               nY, CostArgs<CT>::make(cp), (AT *)D, ticket);
+        else
+            hipLaunchKernelGGL((batch_lane_kernel<CT, AT, DIMT, PM, false>), dim3(grid), dim3(kWave), 0, st,
+                               (const CT *)rowsQ, nQ, (const CT *)rowsY, nullptr, nullptr, cp.dim, offY, nY,
+                               CostArgs<CT>::make(cp), (AT *)D, ticket);
         return hipGetLastError();
     });
 }

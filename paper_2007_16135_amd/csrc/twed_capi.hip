@@ -541,7 +541,10 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
     e = launch_stage(prec, cp, X, TX, (const int64_t *)L.offX, nX, 0, maxX, totX + nX, L.rowsX,
                      (uint32_t *)L.zero, 2, st);
     if (e != hipSuccess) return fail_hip(e, "staging launch");
-    if (!sym && Y) {
+    // one short query reads the caller's collection as it is (no staging
+    // pass); every other sweep reads staged rows
+    const bool lane = lane_eligible(P) && P.cfg.lane_mode != 0;
+    if (!sym && Y && !lane) {
         e = launch_stage(prec, cp, Y, TY, (const int64_t *)L.offY, nY, 0, maxY, totY + nY, L.rowsY, nullptr, 0,
                          st);
         if (e != hipSuccess) return fail_hip(e, "staging launch");
@@ -593,10 +596,9 @@ twed_status batch_enqueue(const BatchPlan &P, const void *X, const void *TX, con
         e = launch_batch_diag_zero(prec, Dk, nX, st);
         if (e != hipSuccess) return fail_hip(e, "diagonal zero launch");
     }
-    const bool lane = lane_eligible(P) && P.cfg.lane_mode != 0;
     if (b.nItems > 0 && lane) {
         // one short query: a lane per pair
-        e = launch_batch_lane(prec, cp, L.rowsX, (int)maxX, L.rowsY, (const int64_t *)L.offY, nY, Dk,
+        e = launch_batch_lane(prec, cp, L.rowsX, (int)maxX, L.rowsY, Y, TY, (const int64_t *)L.offY, nY, Dk,
                               (uint32_t *)L.zero, (int)std::min<int64_t>((nY + 63) / 64, workers), st);
         if (e != hipSuccess) return fail_hip(e, "batch launch");
     } else if (b.nItems > 0) {

@@ -183,10 +183,13 @@ constexpr int kWaveLanes = 64;  // lanes of a wave (gfx950 runs wave64)
 hipError_t launch_batch(Prec prec, const CostParams &cp, const BatchArgs &a, hipStream_t st);
 int batch_kmax(int dimt);
 // One query of at most kLaneMaxQuery samples (staged rows rowsQ) against nY
-// series: one lane per pair, D[j] = TWED(query, Y_j); ticket zeroed.
+// series: one lane per pair, D[j] = TWED(query, Y_j); ticket zeroed.  The
+// series are the staged rows rowsY, or, with Yraw non-null, the caller's
+// arrays Yraw (dim components per sample) and TYraw read directly.
 constexpr int kLaneMaxQuery = 32;
 hipError_t launch_batch_lane(Prec prec, const CostParams &cp, const void *rowsQ, int nQ, const void *rowsY,
-                            const int64_t *offY, int64_t nY, void *D, uint32_t *ticket, int grid, hipStream_t st);
+                            const void *Yraw, const void *TYraw, const int64_t *offY, int64_t nY, void *D,
+                            uint32_t *ticket, int grid, hipStream_t st);
 int batch_max_workers(Prec prec, const CostParams &cp, int kclass = kBatchAll);
 hipError_t launch_batch_diag_zero(Prec prec, void *D, int64_t n, hipStream_t st);
 // dst[0] = src[0] on the device (accumulator type of prec).
