@@ -65,7 +65,23 @@ struct GemmArgs {
     const uint16_t *mask = nullptr;  // bf16 [M][ldc]
     const float *row_norm = nullptr, *col_norm = nullptr;
 };
+// A kAConv GEMM with 2, 4 or 64 channels, 5 taps and a dense [M][N] output (N = 64
+// bf16, or N <= 16 f32) runs on an LDS-staged kernel; any other on the
+// per-wave tile kernel.  Both give the same bits for the staged shapes.
 hipError_t launch_gemm(int out_mode, const GemmArgs &g, int splitk, hipStream_t st);
+// False when the environment sets TWED_CNN_GEMM=generic: then every GEMM and
+// weight gradient takes the per-wave tile kernel (a cross-check of the staged ones).
+bool conv_staged_enabled();
+
+// Weight and bias gradient of one convolution layer in one pass, written (not
+// added) to gWb[0 .. 5 cin cout + cout): dW (kKsize, cin, cout) then db (cout).
+// h [R][cin] and dy [R][cout] bf16 packed rows, row words as in GemmArgs.
+// (cin, cout) in {(64, 64), (64, 4), (2, 64)}; partial: device scratch of
+// conv_wgrad_partial_bytes(R), 16-byte aligned.  Deterministic.
+bool conv_wgrad_fits(int cin, int cout);
+size_t conv_wgrad_partial_bytes(int64_t R);
+hipError_t launch_conv_wgrad(int cin, int cout, const uint16_t *h, const uint32_t *row_info, const uint16_t *dy,
+                             int64_t R, float *partial, float *gWb, hipStream_t st);
 
 // Row words, owning series (optional) and layer-1 features of nSeries packed
 // series.  off: device offsets of those series into X; packed row of sample

@@ -171,7 +171,8 @@ struct EmbedLayout {
     Weights w;
     Acts a;
     float *emb, *demb;
-    void *dy[3];  // bf16 gradients: [R][64] twice (ping-pong), [R][32]
+    void *dy[3];  // bf16 gradients: [R][64] twice (ping-pong), [R][4]
+    float *wpart;  // per-workgroup weight-gradient partials
     size_t total;
 };
 
@@ -189,6 +190,7 @@ EmbedLayout embed_layout(char *base, int64_t n, int64_t total, int64_t maxlen, i
         L.dy[0] = c.take((size_t)total * 64 * 2);
         L.dy[1] = c.take((size_t)total * 64 * 2);
         L.dy[2] = c.take((size_t)total * kC4 * 2);
+        L.wpart = (float *)c.take(conv_wgrad_partial_bytes(total));
     }
     L.total = c.used;
     return L;
@@ -379,23 +381,27 @@ twed_status twed_embed_loss_grad(const float *params, const float *X, const int6
         const int cin = kChan[l], cout = kChan[l + 1];
         float *gW = grad + layer_offset(l);
         float *gb = gW + layer_w_count(l);
-        // dW_l[(tap, c)][n] = sum_r h_l[r + tap - 2][c] dy_l[r][n]
-        GemmArgs g;
-        g.M = kKsize * cin;
-        g.N = cout;
-        g.K = (int)R;
-        g.a_mode = kAConvT;
-        g.A = inputs[l];
-        g.conv_C = cin;
-        g.row_info = a.row_info;
-        g.B = dy_out;
-        g.ldb_k = cout;
-        g.ldb_n = 1;
-        g.C = gW;
-        g.ldc = cout;
-        const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
-        TRY(launch_gemm(kOutAtomic, g, splitk_for(R, tiles), st), "weight gradient");
-        TRY(launch_colsum(dy_out, R, cout, gb, st), "bias gradient");
+        // dW_l[(tap, c)][n] = sum_r h_l[r + tap - 2][c] dy_l[r][n], db_l[n] = sum_r dy_l[r][n]
+        if (conv_staged_enabled() && conv_wgrad_fits(cin, cout)) {
+            TRY(launch_conv_wgrad(cin, cout, inputs[l], a.row_info, dy_out, R, L.wpart, gW, st), "weight gradient");
+        } else {
+            GemmArgs g;
+            g.M = kKsize * cin;
+            g.N = cout;
+            g.K = (int)R;
+            g.a_mode = kAConvT;
+            g.A = inputs[l];
+            g.conv_C = cin;
+            g.row_info = a.row_info;
+            g.B = dy_out;
+            g.ldb_k = cout;
+            g.ldb_n = 1;
+            g.C = gW;
+            g.ldc = cout;
+            const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+            TRY(launch_gemm(kOutAtomic, g, splitk_for(R, tiles), st), "weight gradient");
+            TRY(launch_colsum(dy_out, R, cout, gb, st), "bias gradient");
+        }
         if (l == 0) break;
         // dy_{l-1}[r][c] = sum_{u, n} dy_l[r + u - 2][n] W_l[4 - u][c][n], times [h_l > 0]
         uint16_t *dy_in = (uint16_t *)L.dy[l & 1];

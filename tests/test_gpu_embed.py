@@ -199,6 +199,62 @@ def test_loss_and_gradients_match_oracle(seed):
             assert e < 5e-2 and c > 0.998, (l, name)
 
 
+@pytest.fixture
+def generic_gemm():
+    """Runs a block with TWED_CNN_GEMM=generic (the per-wave tile kernels)."""
+    class Switch:
+        def __enter__(self):
+            os.environ["TWED_CNN_GEMM"] = "generic"
+
+        def __exit__(self, *exc):
+            os.environ.pop("TWED_CNN_GEMM", None)
+    yield Switch()
+    os.environ.pop("TWED_CNN_GEMM", None)
+
+
+def test_staged_conv_kernels_match_tile_kernels(generic_gemm):
+    # The LDS-staged convolutions against the per-wave tile GEMM on a batch of
+    # more rows than 512 weight-gradient workgroups cover in one chunk each
+    # (so workgroups loop over chunks), series of every length class.  The
+    # forward and data-gradient kernels run the same MFMA steps in the same
+    # order: embeddings agree bit for bit.  The loss and the embedding
+    # gradient are summed over pairs with atomics, so from there on two runs
+    # may differ in rounding; the weight gradients also differ in summation
+    # order (the tile kernel adds split-K partials with atomics).
+    rng = np.random.default_rng(77)
+    lengths = np.concatenate([[1, 2, 3, 4, 5, 255, 256, 257], rng.integers(60, 1200, 300)])
+    series = [np.cumsum(rng.standard_normal(int(L))).astype(np.float32) for L in lengths]
+    vec, _ = random_params(77)
+    X, off = pack(series)
+    n = len(series)
+    assert off[-1] > 512 * 256
+    pairs = np.stack([rng.integers(0, n, 512), rng.integers(0, n, 512)], axis=1).astype(np.int32)
+    targets = rng.uniform(0.0, 300.0, 512).astype(np.float32)
+    say(f"staged vs tile conv kernels: {n} series, {off[-1]} rows")
+
+    def run():
+        loss, grad, emb = B.twed_embed_loss_grad(dev(vec), dev(X), off, dev(pairs, torch.int32), dev(targets),
+                                                 emb=torch.empty((n, 128), dtype=torch.float32, device="cuda"))
+        fwd = B.twed_embed_forward(dev(vec), dev(X), off)
+        torch.cuda.synchronize()
+        return float(loss.item()), grad.cpu().numpy(), emb.cpu().numpy(), fwd.cpu().numpy()
+
+    l_s, g_s, e_s, f_s = run()
+    l_s2, g_s2, _, _ = run()
+    with generic_gemm:
+        l_t, g_t, e_t, f_t = run()
+    np.testing.assert_array_equal(f_s, f_t)
+    np.testing.assert_array_equal(e_s, e_t)
+    assert abs(l_s - l_t) <= 1e-6 * abs(l_t) and abs(l_s - l_s2) <= 1e-6 * abs(l_s)
+    assert rel_norm(g_s, g_s2) < 1e-5
+    got, ref = ocnn.unflatten(g_s.astype(np.float64)), ocnn.unflatten(g_t.astype(np.float64))
+    for l in range(4):
+        for name in ("W", "b"):
+            e = rel_norm(got[name][l], ref[name][l])
+            say(f"  layer {l + 1} {name}: rel {e:.2e}")
+            assert e < 1e-4, (l, name)
+
+
 def test_out_of_range_pairs_contribute_nothing():
     series = ragged_series(20)
     vec, _ = random_params(20)
