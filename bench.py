@@ -148,7 +148,9 @@ def parse():
     ap.add_argument("--knn-queries", type=int, default=10_000, help="k-NN queries timed")
     ap.add_argument("--knn-truth", type=int, default=1000,
                     help="queries given exhaustive ground truth (recall sample)")
-    ap.add_argument("--knn-train-steps", type=int, default=20000, help="training steps (2,048 pairs each)")
+    ap.add_argument("--knn-train-steps", type=int, default=40000, help="training steps (2,048 pairs each)")
+    ap.add_argument("--knn-schedule", choices=("cosine", "constant"), default="cosine",
+                    help="learning-rate schedule of the embedding training")
     ap.add_argument("--knn-anchors", type=int, default=4096,
                     help="database series whose exact neighbours are mined for training")
     return ap.parse_args()
@@ -234,7 +236,7 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
 
     tr = knn.Trainer(dbc, nu, lam, seed=0, batch_series=256, pairs_per_step=2048, n_anchors=args.knn_anchors)
     log(f"knn: exact neighbours of {args.knn_anchors} anchors mined in {tr.mine_s:.1f} s")
-    train_s = tr.train(args.knn_train_steps, log_every=5000, log=log)
+    train_s = tr.train(args.knn_train_steps, log_every=5000, log=log, schedule=args.knn_schedule)
     params = tr.params.clone()
     t0 = time.perf_counter()
     index = B.KnnIndex(DB, TDB, db.off, params, nu, lam)
@@ -267,7 +269,7 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
 
     curve = {}
     chosen = None
-    for c in (200, 400, 800, 1600, 3200, 4800, 6400, 8000, 9600, 11200, 12800, 16000, 19200, 25600, 38400,
+    for c in (200, 400, 800, 1600, 3200, 4000, 4800, 5600, 6400, 7200, 8000, 9600, 11200, 12800, 16000, 19200, 25600, 38400,
               51200):
         c = min(c, args.knn_db)
         curve[c] = recall(c)
@@ -293,7 +295,7 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
     out = {"workload": f"{args.knn_db} database / {args.knn_queries} query 1-D FP32 series, lengths U[128,512], "
                        f"half random walks, half noisy sinusoids of 8 classes; nu=1e-3, lambda=1, L1; k=10",
            "train_pairs_labelled": tr.pairs_seen, "train_steps": args.knn_train_steps,
-           "mined_anchors": args.knn_anchors,
+           "mined_anchors": args.knn_anchors, "lr_schedule": args.knn_schedule,
            "mine_s": round(tr.mine_s, 2), "train_s": round(train_s, 2), "index_build_s": round(build_s, 3),
            "recall_sample_queries": nt, "recall_curve": {str(c): round(r, 4) for c, r in curve.items()},
            "recall@10_at_200": round(curve[200], 4), "queries_per_s_at_200": round(q200, 1),

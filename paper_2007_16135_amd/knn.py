@@ -15,6 +15,7 @@ Pair sampling (two kinds per step, both labelled with their exact TWED):
 """
 from __future__ import annotations
 
+import math
 import time
 
 import numpy as np
@@ -129,7 +130,7 @@ class Trainer:
 
     # -- one optimisation step ----------------------------------------------------
 
-    def step(self):
+    def step(self, lr=None):
         torch = self.torch
         series, pairs = self._sample()
         batch = self.db.gather(series)
@@ -140,14 +141,21 @@ class Trainer:
         p32 = p64.to(torch.int32).contiguous()
         B.twed_embed_loss_grad(self.params, batch.X, batch.off, p32, target, grad=self.grad, loss=self.loss)
         self.step_count += 1
-        B.twed_embed_adamw(self.params, self.m, self.v, self.grad, self.step_count, self.lr, self.wd)
+        B.twed_embed_adamw(self.params, self.m, self.v, self.grad, self.step_count, self.lr if lr is None else lr,
+                           self.wd)
         self.pairs_seen += len(pairs)
         return self.loss
 
-    def train(self, steps, log_every=0, log=None):
+    def train(self, steps, log_every=0, log=None, schedule="cosine", lr_floor=0.02):
+        """`steps` optimisation steps.  schedule "cosine": the learning rate
+        falls from lr to lr * lr_floor along a half cosine over the steps;
+        "constant": lr throughout."""
         t0 = time.perf_counter()
         for i in range(steps):
-            loss = self.step()
+            lr = self.lr
+            if schedule == "cosine" and steps > 1:
+                lr = self.lr * (lr_floor + (1.0 - lr_floor) * 0.5 * (1.0 + math.cos(math.pi * i / (steps - 1))))
+            loss = self.step(lr)
             if log_every and (i + 1) % log_every == 0:
                 v = float(loss.item())
                 self.history.append((self.step_count, v))
