@@ -102,11 +102,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def counter_traffic(n, strip_k):
+def counter_traffic(n, strip_k, kernel):
     """HBM-side bytes per launch of the headline sweep from the committed
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy of known size),
     or None when the sweep's sources changed since the counters were taken or
-    the workload differs from the one profiled."""
+    the workload or kernel differs from the one profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "wavefront_8d_n1e6_hbm_counters.md")
     if n != 1_000_000 or strip_k not in (0, 8) or not os.path.exists(path):
@@ -115,6 +115,8 @@ def counter_traffic(n, strip_k):
     for line in open(path):
         if line.startswith("traffic_bytes_per_launch:"):
             traffic = float(line.split(":", 1)[1])
+        elif line.startswith("kernel:"):
+            ok &= line.split(":", 1)[1].strip() == kernel
         elif line.startswith("source_sha256 "):
             name, digest = line[len("source_sha256 "):].split(":", 1)
             src = os.path.join(ROOT, "paper_2007_16135_amd", "csrc", name.strip())
@@ -507,8 +509,15 @@ def main():
                    "cells_per_step": cells, "result": value},
         "roofline": roofline_of(MIX_8D_L2_ACC64, cells / kern_s / 1e9, peaks),
     }
-    result["roofline"].update({"traffic": counter_traffic(n, args.strip_k),
-                               "kernel": "wavefront_kernel<float,double,8,L2,K>", "kernel_avg_s": kern_s})
+    plan = tw.twed_pair_config(n, n, 8, c.nu, c.lam, c.p, "f32_acc64", strip_k=args.strip_k)
+    if plan["wide_strips"] > 0:
+        kname = "wavefront_mixed_kernel<float,double,8,L2,%d,%d,%d>" % (plan["strip_k"], plan["strip_k"] - 1,
+                                                                          plan["group"])
+    else:
+        kname = "wavefront_kernel<float,double,8,L2,%d,%d>" % (plan["strip_k"], plan["group"])
+    result["config"]["strips"] = plan
+    result["roofline"].update({"traffic": counter_traffic(n, args.strip_k, kname),
+                               "kernel": kname, "kernel_avg_s": kern_s})
     if peaks:
         result["measured_peaks"] = peaks
 

@@ -162,6 +162,20 @@ twed_status twed_pair_tune(const void *A, const void *TA, int64_t nA,
                            const twed_params *prm, void *workspace, size_t ws_bytes,
                            hipStream_t stream, int32_t *strip_k, int32_t *group);
 
+/* The strip layout a twed_pair call with these arguments would sweep (no
+ * device work; the device must be current).  Strips of *strip_k columns per
+ * lane in workgroups of *group strips; when uniform strips would leave
+ * workgroup slots of the device empty, the first *wide_strips strips hold
+ * *strip_k columns per lane and the rest *strip_k - 1 (*wide_strips is 0
+ * for uniform strips); *strips is the strip count.  A strip starts one
+ * pipeline lag after its left neighbour (section "Improved Time Warp Edit
+ * Distance": cell (r, c) needs the cell on its left), so narrower strips on
+ * the right end sooner.  Any output pointer may be NULL.  Errors: as
+ * twed_pair's argument checks, TWED_ERR_INVALID for algo ==
+ * TWED_ALGO_DIAGONAL. */
+twed_status twed_pair_config(int64_t nA, int64_t nB, const twed_params *prm, int32_t *strip_k,
+                             int32_t *group, int64_t *wide_strips, int64_t *strips);
+
 /* Empties the tuning cache (single-pair and batch choices). */
 void twed_tune_clear(void);
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "twed_batch_plan_create", "twed_batch_plan_run", "twed_batch_plan_destroy", "twed_batch_plan_stage_y",
     "twed_batch_plan_tune", "twed_batch_plan_config", "twed_tune_save", "twed_tune_load",
     "twed_status_string", "twed_last_error", "twed_stream_check", "twed_version",
-    "twed_pair_tune", "twed_tune_clear",
+    "twed_pair_tune", "twed_tune_clear", "twed_pair_config",
     "twed_pair_tile_workspace_size", "twed_pair_tile", "twed_pair_path_workspace_size", "twed_pair_path",
     "twed_dp_workspace_size", "twed_dp", "twed_dp_path_workspace_size", "twed_dp_path",
     "twed_embed_param_count", "twed_embed_max_length", "twed_embed_set_limits", "twed_embed_workspace_size",
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.twed_pair_tune.restype = ctypes.c_int
     L.twed_tune_clear.argtypes = []
+    L.twed_pair_config.argtypes = [_i64, _i64, _pp, _i32p, _i32p, _i64p, _i64p]
+    L.twed_pair_config.restype = ctypes.c_int
     L.twed_pair_tile_workspace_size.argtypes = [_i64, _i64, _pp]
     L.twed_pair_tile_workspace_size.restype = ctypes.c_size_t
     L.twed_pair_tile.argtypes = [_vp, _vp, _i64, _vp, _vp, _i64, _pp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp,
@@ -432,6 +434,21 @@ def twed_pair_tune(A, TA, B, TB, nu=1e-3, lam=1.0, p=1.0, precision="f64", acc64
     _check(L.twed_pair_tune(A2.data_ptr(), TA.data_ptr(), nA, B2.data_ptr(), TB.data_ptr(), nB, ctypes.byref(prm),
                             ws.data_ptr(), ws.numel(), _stream(stream), ctypes.byref(k), ctypes.byref(g)))
     return int(k.value), int(g.value)
+
+
+def twed_pair_config(nA, nB, dim=1, nu=1e-3, lam=1.0, p=1.0, precision="f64", strip_k=0, acc64_threshold=0):
+    """The strip layout twed_pair would sweep for these arguments, as a dict:
+    strip_k (columns per lane), group (strips per workgroup), wide_strips (the
+    strips of strip_k columns before those of strip_k - 1 in a two-width
+    sweep, 0 for uniform strips) and strips.  Needs a current GPU; launches
+    nothing."""
+    prm = make_params(nu, lam, p, dim, precision, "auto", strip_k, acc64_threshold)
+    L = load_library()
+    k, g = ctypes.c_int32(0), ctypes.c_int32(0)
+    w, n = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(L.twed_pair_config(int(nA), int(nB), ctypes.byref(prm), ctypes.byref(k), ctypes.byref(g),
+                              ctypes.byref(w), ctypes.byref(n)))
+    return {"strip_k": int(k.value), "group": int(g.value), "wide_strips": int(w.value), "strips": int(n.value)}
 
 
 def twed_tune_clear():

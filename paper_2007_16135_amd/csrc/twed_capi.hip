@@ -168,6 +168,136 @@ bool tuned_choice(Prec prec, const CostParams &cp, int64_t nB, SweepChoice *out)
     return true;
 }
 
+// ---- strips of two widths ---------------------------------------------------------------
+//
+// With every strip resident, strip s starts lag_s of its own steps after
+// strip s-1 and then runs nA + 63 steps: the lag is 64 + 16 inside a group
+// (the lane skew and the in-group handoff interval) and 64 + 64 where the
+// boundary leaves the group through a global window.  A step of K columns
+// per lane costs about K + 1/2 cells of time (the boundary shifts, loads and
+// stores of the step).  The sweep ends when its last strip of either width
+// ends.  choose_mixed_split returns the number s1 of wide strips of a layout
+// that minimises that end with at most `slots` strips in all (every strip
+// resident), or 0 when no split beats uniform strips of the wide width by
+// 1% (or when uniform strips would not all be resident either).
+int64_t choose_mixed_split(const MixedLayout &L, int64_t nA, int64_t nB, int64_t slots)
+{
+    const int K = L.wide, K2 = L.narrow, G = L.group;
+    constexpr double h = 0.5, lag_in = 80.0, lag_out = 128.0;
+    auto lags = [&](int64_t n) { return lag_in * (double)n + (lag_out - lag_in) * (double)(n / G); };
+    const double run = (double)(nA + 63);
+    const int64_t su = (nB + 64 * K - 1) / (64 * K);
+    if (su > slots) return 0;
+    double best = 0.99 * ((K + h) * lags(su - 1) + run * (K + h));
+    int64_t best_s1 = 0;
+    for (int64_t s1 = 1; s1 < su; ++s1) {
+        const int64_t S = s1 + (nB - 64 * K * s1 + 64 * K2 - 1) / (64 * K2);
+        if (S > slots) continue;
+        const double end_wide = (K + h) * lags(s1 - 1) + run * (K + h);
+        const double start_last = (K + h) * lags(s1) + (K2 + h) * (lags(S - 1) - lags(s1));
+        const double end = std::max(end_wide, start_last + run * (K2 + h));
+        if (end < best) {
+            best = end;
+            best_s1 = s1;
+        }
+    }
+    return best_s1;
+}
+
+// Configuration of one single-pair strip sweep.
+struct SweepPlan {
+    int K, G, sub_shift;
+    int layout;       // two-width layout (kMixedLayouts), when s1 > 0
+    int64_t s1;       // wide strips of a two-width sweep (0: uniform strips of K)
+    int64_t nStrips;
+    int grid;         // workgroups launched
+};
+
+twed_status plan_pair_sweep(Prec prec, const CostParams &cp, const twed_params *prm, int64_t nA, int64_t nB,
+                            bool dump, const SweepChoice *force, SweepPlan *plan)
+{
+    SweepChoice tuned{};
+    const bool have_tuned = !force && !dump && prm->strip_k == 0 && tuned_choice(prec, cp, nB, &tuned);
+    int K = force ? force->K : (have_tuned ? tuned.K : choose_k(prm, nB, prec, cp));
+    if (dump) {
+        // cell dumps exist for narrow strips only (a validation aid)
+        if (prm->strip_k > 2) return fail(TWED_ERR_UNSUPPORTED, "twed_pair_matrix takes strip_k 0, 1 or 2");
+        K = std::min(K, 2);
+    }
+    plan->K = K;
+    plan->s1 = 0;
+    plan->nStrips = (nB + 64 * K - 1) / (64 * K);
+    // Strips per workgroup: in-group handoffs go through LDS, one in G
+    // through global memory.  The widest group that still leaves about
+    // three groups for every four CUs and whose kernel keeps to registers
+    // (eight waves put two on each SIMD, which halves the registers a lane
+    // may hold: too few for the widest high-dimensional strips); cell dumps
+    // use single-wave groups.
+    // TWED_WAVEFRONT_GROUP
+    // (1, 4 or 8) and TWED_WAVEFRONT_SUB (in-group handoff rows: 8, 16 or 32)
+    // override the choices for tuning runs.
+    const int64_t cus = std::max(1, device_simds() / 4);
+    plan->G = 1;
+    for (int G : {8, 4})
+        if (plan->nStrips * 4 >= (int64_t)G * cus * 3 && wavefront_scratch_bytes(prec, cp, K, G) == 0) {
+            plan->G = G;
+            break;
+        }
+    if (dump) plan->G = 1;
+    if (const char *env = std::getenv("TWED_WAVEFRONT_GROUP")) {
+        const int G = std::atoi(env);
+        if ((G == 1 || G == 4 || G == 8) && !dump) plan->G = G;
+    }
+    plan->sub_shift = 4;
+    if (const char *env = std::getenv("TWED_WAVEFRONT_SUB")) {
+        const int v = std::atoi(env);
+        if (v == 8 || v == 16 || v == 32) plan->sub_shift = v == 8 ? 3 : (v == 16 ? 4 : 5);
+    }
+    if (have_tuned) {
+        plan->G = tuned.G;
+        plan->sub_shift = tuned.sub_shift;
+    }
+    if (force) {
+        plan->G = force->G;
+        plan->sub_shift = force->sub_shift;
+    }
+    // Strips of two widths where the widest strips in groups of eight would
+    // leave workgroup slots empty: the first compiled, register-resident
+    // layout of kMixedLayouts that beats uniform strips.
+    // TWED_WAVEFRONT_LAYOUT picks one layout (its index; -1 none) and
+    // TWED_WAVEFRONT_MIXED the number of wide strips (0 none); results do not
+    // depend on either.
+    plan->layout = -1;
+    if (!dump && K == 8 && plan->G == 8 && plan->nStrips > 1) {
+        int only = -2;
+        if (const char *env = std::getenv("TWED_WAVEFRONT_LAYOUT")) only = std::atoi(env);
+        int64_t forced = -1;
+        if (const char *env = std::getenv("TWED_WAVEFRONT_MIXED")) forced = std::max<int64_t>(0, std::atoll(env));
+        for (int m = 0; m < kNumMixedLayouts && forced != 0; ++m) {
+            if (only != -2 && m != only) continue;
+            if (!wavefront_mixed_compiled(prec, cp, m) || wavefront_mixed_scratch_bytes(prec, cp, m) != 0) continue;
+            const MixedLayout &L = kMixedLayouts[m];
+            const int mworkers = wavefront_mixed_max_workers(prec, cp, m);
+            if (mworkers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+            const int64_t su = (nB + 64 * L.wide - 1) / (64 * L.wide);
+            int64_t s1 = forced > 0 ? forced : choose_mixed_split(L, nA, nB, (int64_t)mworkers * L.group);
+            s1 = std::min<int64_t>(s1, su - 1);
+            if (s1 <= 0) continue;
+            plan->layout = m;
+            plan->K = L.wide;
+            plan->G = L.group;
+            plan->s1 = s1;
+            plan->nStrips = s1 + (nB - 64 * L.wide * s1 + 64 * L.narrow - 1) / (64 * L.narrow);
+            plan->grid = (int)std::min<int64_t>((plan->nStrips + L.group - 1) / L.group, mworkers);
+            return TWED_OK;
+        }
+    }
+    const int workers = wavefront_max_workers(prec, cp, K, plan->G);
+    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
+    plan->grid = (int)std::min<int64_t>((plan->nStrips + plan->G - 1) / plan->G, workers);
+    return TWED_OK;
+}
+
 // Runs the sweep of one pair whose rows are already staged.
 // `tail` points at the kTailWords words after the flags (zeroed beforehand).
 twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *prm, const void *rowsA,
@@ -199,14 +329,9 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
         if (e != hipSuccess) return fail_hip(e, "diagonal sweep launch");
         return TWED_OK;
     }
-    SweepChoice tuned{};
-    const bool have_tuned = !force && !dump && prm->strip_k == 0 && tuned_choice(prec, cp, nB, &tuned);
-    int K = force ? force->K : (have_tuned ? tuned.K : choose_k(prm, nB, prec, cp));
-    if (dump) {
-        // cell dumps exist for narrow strips only (a validation aid)
-        if (prm->strip_k > 2) return fail(TWED_ERR_UNSUPPORTED, "twed_pair_matrix takes strip_k 0, 1 or 2");
-        K = std::min(K, 2);
-    }
+    SweepPlan plan{};
+    twed_status s = plan_pair_sweep(prec, cp, prm, nA, nB, dump != nullptr, force, &plan);
+    if (s != TWED_OK) return s;
     WavefrontArgs w{};
     w.rowsA = rowsA;
     w.rowsB = rowsB;
@@ -216,48 +341,14 @@ twed_status run_pair_sweep(Prec prec, const CostParams &cp, const twed_params *p
     w.flags = flags;
     w.ticket = tail;
     w.beta = beta;
-    w.nStrips = (nB + 64 * K - 1) / (64 * K);
+    w.nStrips = plan.nStrips;
     w.out = out;
     w.dump = dump;
-    // Strips per workgroup: in-group handoffs go through LDS, one in G
-    // through global memory.  The widest group that still leaves about
-    // three groups for every four CUs and whose kernel keeps to registers
-    // (eight waves put two on each SIMD, which halves the registers a lane
-    // may hold: too few for the widest high-dimensional strips); cell dumps
-    // use single-wave groups.
-    // TWED_WAVEFRONT_GROUP
-    // (1, 4 or 8) and TWED_WAVEFRONT_SUB (in-group handoff rows: 8, 16 or 32)
-    // override the choices for tuning runs.
-    const int64_t cus = std::max(1, device_simds() / 4);
-    w.group = 1;
-    for (int G : {8, 4})
-        if (w.nStrips * 4 >= (int64_t)G * cus * 3 && wavefront_scratch_bytes(prec, cp, K, G) == 0) {
-            w.group = G;
-            break;
-        }
-    if (dump) w.group = 1;
-    if (const char *env = std::getenv("TWED_WAVEFRONT_GROUP")) {
-        const int G = std::atoi(env);
-        if ((G == 1 || G == 4 || G == 8) && !dump) w.group = G;
-    }
-    w.sub_shift = 4;
-    if (const char *env = std::getenv("TWED_WAVEFRONT_SUB")) {
-        const int v = std::atoi(env);
-        if (v == 8 || v == 16 || v == 32) w.sub_shift = v == 8 ? 3 : (v == 16 ? 4 : 5);
-    }
-    if (have_tuned) {
-        w.group = tuned.G;
-        w.sub_shift = tuned.sub_shift;
-    }
-    if (force) {
-        w.group = force->G;
-        w.sub_shift = force->sub_shift;
-    }
-    const int64_t groups = (w.nStrips + w.group - 1) / w.group;
-    int workers = wavefront_max_workers(prec, cp, K, w.group);
-    if (workers <= 0) return fail(TWED_ERR_DEVICE, "occupancy query failed");
-    w.grid = (int)std::min<int64_t>(groups, workers);
-    e = launch_wavefront(prec, cp, K, w, st);
+    w.group = plan.G;
+    w.sub_shift = plan.sub_shift;
+    w.s1 = (int)plan.s1;
+    w.grid = plan.grid;
+    e = plan.s1 > 0 ? launch_wavefront_mixed(prec, cp, plan.layout, w, st) : launch_wavefront(prec, cp, plan.K, w, st);
     if (e != hipSuccess) return fail_hip(e, "wavefront sweep launch");
     return TWED_OK;
 }
@@ -763,6 +854,25 @@ twed_status twed_pair(const void *A, const void *TA, int64_t nA, const void *B, 
 {
     last_error().clear();
     return pair_impl(A, TA, nA, B, TB, nB, prm, out, nullptr, workspace, ws_bytes, stream);
+}
+
+twed_status twed_pair_config(int64_t nA, int64_t nB, const twed_params *prm, int32_t *strip_k, int32_t *group,
+                             int64_t *wide_strips, int64_t *strips)
+{
+    last_error().clear();
+    twed_status s = check_params(prm);
+    if (s != TWED_OK) return s;
+    if (nA < 1 || nB < 1) return fail(TWED_ERR_INVALID, "series lengths must be >= 1");
+    if (nA > kMaxLen || nB > kMaxLen) return fail(TWED_ERR_UNSUPPORTED, "series longer than 2^31 - 130");
+    if (prm->algo == TWED_ALGO_DIAGONAL) return fail(TWED_ERR_INVALID, "the per-diagonal sweep has no strips");
+    SweepPlan plan{};
+    s = plan_pair_sweep(resolve(prm, std::max(nA, nB)), cost_params(prm), prm, nA, nB, false, nullptr, &plan);
+    if (s != TWED_OK) return s;
+    if (strip_k) *strip_k = plan.K;
+    if (group) *group = plan.G;
+    if (wide_strips) *wide_strips = plan.s1;
+    if (strips) *strips = plan.nStrips;
+    return TWED_OK;
 }
 
 twed_status twed_pair_noalloc(const void *A, const void *TA, int64_t nA, const void *B, const void *TB,

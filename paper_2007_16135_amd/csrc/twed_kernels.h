@@ -69,8 +69,24 @@ struct WavefrontArgs {
     int grid;           // workgroups
     int group;          // waves (consecutive strips) per workgroup: 1, 4 or 8
     int sub_shift;      // in-group handoff every 1 << sub_shift rows (3, 4 or 5)
+    int s1;             // two strip widths (launch_wavefront_mixed): strips before s1 hold K columns per lane
 };
 hipError_t launch_wavefront(Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, hipStream_t st);
+// Strips of two widths (wavefront_mixed.hip): layout m sweeps strips 0 .. a.s1-1
+// with kMixedLayouts[m].wide columns per lane and the others with .narrow,
+// in workgroups of .group strips.
+struct MixedLayout {
+    int wide, narrow, group;
+};
+constexpr MixedLayout kMixedLayouts[] = {{8, 7, 8}};
+constexpr int kNumMixedLayouts = 1;
+// True if the two-width sweep of this layout is compiled for this
+// (precision, dimension, distance).
+bool wavefront_mixed_compiled(Prec prec, const CostParams &cp, int layout);
+hipError_t launch_wavefront_mixed(Prec prec, const CostParams &cp, int layout, const WavefrontArgs &a,
+                                  hipStream_t st);
+int wavefront_mixed_max_workers(Prec prec, const CostParams &cp, int layout);
+size_t wavefront_mixed_scratch_bytes(Prec prec, const CostParams &cp, int layout);
 // FP32 pairs longer than this get a per-diagonal cost offset.
 constexpr int64_t kOffsetMinLength = 4096;
 // Writes the FP32 cost offset of one staged pair to beta (one cost element).

@@ -8,8 +8,14 @@ namespace twed {
 
 
 // Polls of a predecessor's progress word before a wave gives up (tens of
-// seconds).
-constexpr uint32_t kMaxPolls = 1u << 23;
+// seconds either way: an LDS poll takes about 0.1 us with its sleep, a
+// global one a few us).
+constexpr uint32_t kMaxPollsLds = 1u << 28;
+constexpr uint32_t kMaxPollsGlobal = 1u << 24;
+// The error word (a global load, a few us) is read once every kErrEvery
+// polls, so a waiting wave notices its predecessor's progress within one
+// poll.
+constexpr uint32_t kErrEvery = 64;
 
 template <typename AT>
 struct alignas(2 * sizeof(AT)) Pair2 {
@@ -42,16 +48,17 @@ __device__ __forceinline__ uint32_t load_lds_progress(const uint32_t *p)
 
 // Bounded wait until *p >= need (uniform across the wave).  A wave that gives
 // up marks the error word (the result strip then reports NaN) and carries
-// on, and once the word is set no wave waits any more, so every wave still
-// reaches the end of the grid after at most one time-out.
+// on, and once the word is set no wave waits any more (it is read every
+// kErrEvery polls), so every wave still reaches the end of the grid after at
+// most one time-out.
 template <bool LDS>
 __device__ __forceinline__ void wait_progress(const uint32_t *p, uint32_t need, uint32_t *err)
 {
     uint32_t polls = 0;
     while ((LDS ? load_lds_progress(p) : load_progress(p)) < need) {
-        if (load_progress(err) != 0u) break;
+        if (polls % kErrEvery == kErrEvery - 1 && load_progress(err) != 0u) break;
         __builtin_amdgcn_s_sleep(1);
-        if (++polls > kMaxPolls) {
+        if (++polls > (LDS ? kMaxPollsLds : kMaxPollsGlobal)) {
             __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
@@ -120,7 +127,8 @@ constexpr bool kStripCompiled = DIMT <= 16 || K <= 2;
 // row, and in a tile the lane loads its top-row cells at the step where it
 // sits on row 0, so that row 1 starts from them.
 template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC, bool DIRS>
-__device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g, int s, const CT *__restrict__ rowsA,
+__device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g, int s, int cbase,
+                                            const CT *__restrict__ rowsA,
                                             const CT *__restrict__ rowsB, int nA, int nB, const CostArgs<CT> &ca,
                                             Pair2<AT> *bnd, uint32_t *flags, uint32_t *err, int nStrips, CT beta,
                                             AT *out, AT *dump, int sub_shift, const TileIO<AT> &io)
@@ -135,8 +143,8 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     // Row t - lane of A, the row lane `lane` works on at step t: a pointer
     // that advances by one row per step (a 64-bit add, no multiply).
     const CT *row_ptr = rowsA - (ptrdiff_t)lane * S;
-    // ---- columns of this lane
-    const int c0 = 1 + s * W + lane * K;
+    // ---- columns of this lane (the strip's first column is 1 + cbase)
+    const int c0 = 1 + cbase + lane * K;
     Lane<CT, AT, DIMT, K> L;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -162,10 +170,10 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     const uint32_t *in_flag = flags + (g > 0 ? g - 1 : 0);
     uint32_t *out_flag = flags + g;
 
-    const int last_strip = (nB - 1) / W;
-    const int qs = (nB - 1) - last_strip * W;
+    // column nB sits in the last strip, at lane lstar, column jstar
+    const bool result_strip = s == nStrips - 1;
+    const int qs = (nB - 1) - cbase;
     const int lstar = qs / K, jstar = qs - (qs / K) * K;
-    const bool result_strip = s == last_strip;
 
     // Operands shifted in from lane l-1 after each step: sh_l is the left
     // operand DP(r, c0-1) of the next step, sh_xo its up-left operand
@@ -180,21 +188,30 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     if constexpr (TILE) {
         // X(0, c0 - 1) of this strip: from the top row, else the corner
         AT x0 = INF;
-        if (io.top != nullptr) x0 = io.top[s * W].x;
+        if (io.top != nullptr) x0 = io.top[cbase].x;
         else if (s == 0) x0 = io.left != nullptr ? io.left[0].x : AT(0);
         sh_x = lane == 0 ? x0 : INF;
-        if (io.ckcol != nullptr && has_out && ((s + 1) * W) % io.ck_cols == 0)
-            ck_col = io.ckcol + (size_t)((s + 1) * W / io.ck_cols - 1) * (size_t)(nA + 1);
+        if (io.ckcol != nullptr && has_out && (cbase + W) % io.ck_cols == 0)
+            ck_col = io.ckcol + (size_t)((cbase + W) / io.ck_cols - 1) * (size_t)(nA + 1);
     }
 
     const int T = nA + kWave;  // lane 63 reaches row nA at step nA + 63
-    // Rows of A are loaded kAhead steps before their use: one step of 64*K
-    // columns hides the load behind K cells of work, which is enough for
-    // wide strips; narrow strips of small samples keep a ring of kAhead + 1
-    // rows (kAhead + 1 divides every sub-chunk of 8, 16 or 32 steps).  A
-    // deeper ring for one-column strips (7 rows ahead) pushed the tile
-    // kernels of eight-wave groups past 256 registers.
-    constexpr int kAhead = (K <= 2 && DIMT <= 8) ? 3 : 1;
+    // The last strip stops once lane lstar has swept row nA (its lanes past
+    // lstar hold columns beyond nB): the result is then in that lane's
+    // registers, and the step loop carries no test for it.
+    const int T_run = result_strip ? nA + lstar + 1 : T;
+    // Rows of A are loaded kAhead steps before their use, from a ring of
+    // kAhead + 1 rows (kAhead + 1 divides every sub-chunk of 8, 16 or 32
+    // steps).  Narrow strips of small samples load three rows ahead.  So do
+    // pair sweeps of wide strips whose ring of rows stays small next to the
+    // lane's columns (at most 96 registers for the K columns' rows), e.g. 8-D
+    // FP32 rows: consecutive groups on one XCD read rows far apart, so a row
+    // often comes from the Infinity Cache, and one step of even eight
+    // columns does not hide that latency.  Tile sweeps of wide strips load
+    // one row ahead (a deeper ring pushed the tile kernels of eight-wave
+    // groups past 256 registers), and so do large samples.
+    constexpr int kRowRegs = Row<CT, DIMT>::kStride * (int)sizeof(CT) / 4;
+    constexpr int kAhead = (DIMT <= 8 && (K <= 2 || (!TILE && kRowRegs * K <= 64))) ? 3 : 1;
     // lane 0 prefetches up to row nA + 63 + kAhead: inside the zero rows
     // that end every packed buffer
     static_assert(kWave - 1 + kAhead <= kRowPadTail, "row prefetch runs past the buffer padding");
@@ -224,10 +241,10 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     const int in_mask = in_lds ? kRing - 1 : kWindow - 1;
     Pair2<AT> *const out_ring = out_lds ? &sh.ring[w < G - 1 ? w : 0][0] : &sh.out_stage[0];
 
-    for (int t0 = 0; t0 < T; t0 += kSub) {
+    for (int t0 = 0; t0 < T_run; t0 += kSub) {
         const int q = (t0 >> sub_shift) & ((kWindow >> sub_shift) - 1);  // sub-chunk within the window
         const int wb = t0 - q * kSub;                          // window start
-        const int steps = T - t0 < kSub ? T - t0 : kSub;
+        const int steps = T_run - t0 < kSub ? T_run - t0 : kSub;
         if (in_global && q == 0) {
             if (!TILE || s > 0) {  // a tile's left column is there from the start
                 const uint32_t need = (uint32_t)(t0 + kWindow < nA ? t0 + kWindow : nA);
@@ -344,26 +361,15 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
                                              : L.up[j];
                 }
             }
-            // The result is wave-uniform; every lane stores it (one
-            // transaction): no lane-conditional branch in the step loop.
-            if (result_strip && t == nA + lstar) {
-                AT res = L.up[0];
-#pragma unroll
-                for (int j = 1; j < K; ++j)
-                    if (j == jstar) res = L.up[j];
-                res = lane_value(res, lstar);
-                if (kShifted<AT>) res = (AT)((double)res + (double)beta * (double)(nA + nB));
-                if (load_progress(err) != 0u) res = __builtin_nan("");
-                out[0] = res;
-            }
-
             sh_xo = sh_x;
             sh_l = shift_in(left, nb.dp);
             sh_x = shift_in(xl, nb.x);
             if (has_out && lane == kWave - 1) {
-                // lane 63 holds row t - 63 of the strip's right boundary
-                const int r = t - (kWave - 1);
-                out_ring[(r >= 1 && r <= nA) ? (r & (kRing - 1)) : kRing] = Pair2<AT>{left, xl};
+                // Lane 63 holds row t - 63 of the strip's right boundary.
+                // Rows -63 .. 0 of the first 64 steps land in the slots of
+                // rows 65 .. 128, which are written again with those rows
+                // (steps 128 .. 191) before anyone may read them.
+                out_ring[(t - (kWave - 1)) & (kRing - 1)] = Pair2<AT>{left, xl};
             }
         };
         auto run = [&]<bool SP>() {
@@ -453,29 +459,33 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
             }
         }
     }
+    if (result_strip) {
+        // DP(nA, nB): column jstar of lane lstar after its sweep of row nA
+        // (wave-uniform; every lane stores the same value)
+        AT res = L.up[0];
+#pragma unroll
+        for (int j = 1; j < K; ++j)
+            if (j == jstar) res = L.up[j];
+        res = lane_value(res, lstar);
+        if (kShifted<AT>) res = (AT)((double)res + (double)beta * (double)(nA + nB));
+        if (load_progress(err) != 0u) res = __builtin_nan("");
+        out[0] = res;
+    }
 }
 
 // Persistent workgroups of G waves.  A workgroup claims a group g of G
 // consecutive strips from an atomic ticket (wave 0 claims, LDS broadcasts),
 // so the group it waits for has always been claimed by a running workgroup:
 // no co-residency assumption, no deadlock.  Inside the group, wave w sweeps
-// strip g*G + w.
+// strip g*G + w: body(w, g, s).
 //
 // Two global slots suffice: group g+2 writes row r of its boundary only
 // after group g+1 has read row r from the slot both use (it reads a row
 // before its own last wave can produce that row).
-template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC = kRecTwed,
-          bool DIRS = false>
-__global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restrict__ rowsA,
-                                                             const CT *__restrict__ rowsB, int nA, int nB,
-                                                             CostArgs<CT> ca, Pair2<AT> *bnd, uint32_t *flags,
-                                                             uint32_t *ticket, uint32_t *err, int nStrips,
-                                                             const CT *beta_ptr, AT *out, AT *dump, int sub_shift,
-                                                             TileIO<AT> io)
+template <typename AT, int G, typename Body>
+__device__ __forceinline__ void claim_groups(GroupShared<AT, G> &sh, uint32_t *ticket, int nStrips, Body &&body)
 {
-    __shared__ GroupShared<AT, G> sh;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const CT beta = kShifted<AT> ? beta_ptr[0] : CT(0);
     const int nGroups = (nStrips + G - 1) / G;
     for (;;) {
         __syncthreads();  // the previous group is done with the LDS
@@ -491,10 +501,57 @@ __global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restri
         const int g = (int)__hip_atomic_load(&sh.ticket[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (g >= nGroups) break;
         const int s = g * G + w;
-        if (s < nStrips)
-            sweep_strip<CT, AT, DIMT, PM, K, G, DUMP, TILE, REC, DIRS>(sh, w, g, s, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
-                                                            nStrips, beta, out, dump, sub_shift, io);
+        if (s < nStrips) body(w, g, s);
     }
+}
+
+// Strips of one width: strip s starts at column 1 + s*64*K.
+template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool DUMP, bool TILE, int REC = kRecTwed,
+          bool DIRS = false>
+__global__ __launch_bounds__(kWave * G) void wavefront_kernel(const CT *__restrict__ rowsA,
+                                                             const CT *__restrict__ rowsB, int nA, int nB,
+                                                             CostArgs<CT> ca, Pair2<AT> *bnd, uint32_t *flags,
+                                                             uint32_t *ticket, uint32_t *err, int nStrips,
+                                                             const CT *beta_ptr, AT *out, AT *dump, int sub_shift,
+                                                             TileIO<AT> io)
+{
+    __shared__ GroupShared<AT, G> sh;
+    const CT beta = kShifted<AT> ? beta_ptr[0] : CT(0);
+    claim_groups<AT, G>(sh, ticket, nStrips, [&](int w, int g, int s) {
+        sweep_strip<CT, AT, DIMT, PM, K, G, DUMP, TILE, REC, DIRS>(sh, w, g, s, s * kWave * K, rowsA, rowsB, nA, nB,
+                                                                   ca, bnd, flags, err, nStrips, beta, out, dump,
+                                                                   sub_shift, io);
+    });
+}
+
+// Strips of two widths: strips 0 .. s1-1 hold K columns per lane, the rest
+// K2 < K.  A strip starts one pipeline lag (in its own steps) after the one
+// before it and runs nA + 63 steps, so with every strip resident the sweep
+// ends when the last strip does: narrower strips at the end of the row
+// finish sooner, and the spare workgroup slots that uniform strips would
+// leave idle take the extra strips.  Cells and their arithmetic do not
+// depend on the strip widths.
+template <typename CT, typename AT, int DIMT, int PM, int K, int K2, int G>
+__global__ __launch_bounds__(kWave * G) void wavefront_mixed_kernel(const CT *__restrict__ rowsA,
+                                                                   const CT *__restrict__ rowsB, int nA, int nB,
+                                                                   CostArgs<CT> ca, Pair2<AT> *bnd, uint32_t *flags,
+                                                                   uint32_t *ticket, uint32_t *err, int nStrips,
+                                                                   int s1, const CT *beta_ptr, AT *out,
+                                                                   int sub_shift)
+{
+    static_assert(K2 < K, "the second width is the narrower one");
+    __shared__ GroupShared<AT, G> sh;
+    const CT beta = kShifted<AT> ? beta_ptr[0] : CT(0);
+    claim_groups<AT, G>(sh, ticket, nStrips, [&](int w, int g, int s) {
+        if (s < s1)
+            sweep_strip<CT, AT, DIMT, PM, K, G, false, false, kRecTwed, false>(
+                sh, w, g, s, s * kWave * K, rowsA, rowsB, nA, nB, ca, bnd, flags, err, nStrips, beta, out,
+                nullptr, sub_shift, TileIO<AT>{});
+        else
+            sweep_strip<CT, AT, DIMT, PM, K2, G, false, false, kRecTwed, false>(
+                sh, w, g, s, s1 * kWave * K + (s - s1) * kWave * K2, rowsA, rowsB, nA, nB, ca, bnd, flags, err,
+                nStrips, beta, out, nullptr, sub_shift, TileIO<AT>{});
+    });
 }
 
 template <typename CT, typename AT, int DIMT, int PM, int K, int G, bool TILE, int REC = kRecTwed,

@@ -110,6 +110,23 @@ def test_pair_noalloc_host_checks(L):
     assert "twed_pair_noalloc" in msg and str(limit) in msg
 
 
+def test_pair_config_host_checks(L):
+    """twed_pair_config validates its arguments before touching the device."""
+    prm = binding.make_params(dim=8, precision="f32_acc64")
+    k, g = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    w, n = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    outs = (ctypes.byref(k), ctypes.byref(g), ctypes.byref(w), ctypes.byref(n))
+    assert L.twed_pair_config(0, 10, ctypes.byref(prm), *outs) == INVALID
+    assert L.twed_pair_config(10, -1, ctypes.byref(prm), *outs) == INVALID
+    assert L.twed_pair_config(10, 10, None, *outs) == INVALID
+    assert L.twed_pair_config(1 << 31, 10, ctypes.byref(prm), *outs) == UNSUPPORTED
+    bad = binding.make_params(p=0.5)
+    assert L.twed_pair_config(10, 10, ctypes.byref(bad), *outs) == INVALID
+    diag = binding.make_params(algo="diagonal")
+    assert L.twed_pair_config(10, 10, ctypes.byref(diag), *outs) == INVALID
+    assert (k.value, g.value, w.value, n.value) == (-1, -1, -1, -1)  # nothing written on error
+
+
 def test_pair_matrix_needs_dp(L):
     good = tw.make_params()
     assert L.twed_pair_matrix(FAKE, FAKE, 4, FAKE, FAKE, 4, ctypes.byref(good), FAKE, None, None, 0,

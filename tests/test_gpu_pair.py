@@ -295,6 +295,58 @@ def test_strip_groups_long_pair_vs_oracle(monkeypatch):
         assert abs(v - ref) <= 1e-6 * abs(ref), (k, v, ref)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_acc64"])
+def test_two_strip_widths_bitwise(prec, monkeypatch):
+    """Strips of two widths (8 then 7 columns per lane in groups of eight;
+    TWED_WAVEFRONT_MIXED = number of wide strips) cover the same cells with
+    the same arithmetic as uniform strips: results agree to the bit for every
+    split, including splits inside a group and a last strip holding only a
+    few columns; FP64 also against the oracle."""
+    monkeypatch.setenv("TWED_WAVEFRONT_GROUP", "8")
+    layout, wide = 0, 8
+    for nA, nB in ((1500, 64 * wide * 11 - 3), (900, 64 * wide * 17 + 5)):
+        c = synth.random_pair(51, 52, nA, nB, 3, irregular=True, nu=0.02, lam=0.6, p=2.0)
+        monkeypatch.setenv("TWED_WAVEFRONT_MIXED", "0")
+        ref = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec, algo="wavefront", strip_k=8)
+        if prec == "f64":
+            want = oracle.twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p)
+            assert abs(ref - want) <= RTOL["f64"] * abs(want), (ref, want)
+        su = (nB + 64 * wide - 1) // (64 * wide)
+        for s1 in (1, 3, 8, su - 2, su - 1):
+            monkeypatch.setenv("TWED_WAVEFRONT_MIXED", str(s1))
+            cfg = tw.twed_pair_config(nA, nB, 3, c.nu, c.lam, c.p, prec, strip_k=8)
+            assert cfg["wide_strips"] == s1 and cfg["strip_k"] == wide, cfg
+            say(f"two widths {prec} layout {layout} {nA}x{nB} s1={s1}")
+            v = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, prec, algo="wavefront", strip_k=8)
+            assert v == ref, (prec, layout, nA, nB, s1, v, ref)
+
+
+def test_two_strip_widths_long_pair_vs_oracle(monkeypatch):
+    """The split the host picks for a pair long enough to fill the device
+    (8-D, FP32 costs with FP64 accumulators) against the FP64 oracle on its
+    1e4 x 1e4 prefix through the prefix property: the sweep of the
+    prefixes with forced two-width strips equals the oracle, and the
+    long pair's distance is bitwise the same with and without two widths."""
+    c = synth.single_pair_8d(10000).astype(np.float32).astype(np.float64)
+    ref = oracle.twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, rows=True)
+    monkeypatch.setenv("TWED_WAVEFRONT_GROUP", "8")
+    monkeypatch.setenv("TWED_WAVEFRONT_MIXED", "6")
+    v = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f32_acc64", strip_k=8)
+    assert abs(v - ref) <= RTOL["f32_acc64"] * abs(ref), (v, ref)
+    long = synth.single_pair_8d(600_000)
+    dt = torch.float32
+    A, TA, B, TB = (dev(np.asarray(x, np.float32), dt) for x in (long.A, long.TA, long.B, long.TB))
+    out = {}
+    for mixed in ("0", None):
+        if mixed is None:
+            monkeypatch.delenv("TWED_WAVEFRONT_MIXED", raising=False)
+        else:
+            monkeypatch.setenv("TWED_WAVEFRONT_MIXED", mixed)
+        say(f"two widths 8-D n=600000 mixed={mixed}")
+        out[mixed] = float(tw.twed_pair(A, TA, B, TB, long.nu, long.lam, long.p, "f32_acc64").item())
+    assert out["0"] == out[None], out
+
+
 def test_tuner_picks_a_configuration_and_keeps_results():
     """twed_pair_tune times the sweep configurations and caches the fastest;
     the tuned call returns the bit-identical distance."""
