@@ -35,8 +35,8 @@ import numpy as np  # noqa: E402
 # TFLOP/s and FP64 vector 78.6 TFLOP/s, i.e. 78.6 T and 39.3 T lane operations
 # per second (an FMA is one lane operation, two flops).  Transcendentals (the
 # FP32 square root) run at a quarter of the FP32 rate.  The FP64 square root
-# (correctly rounded: a reciprocal-root seed and refinement steps) is priced
-# as one quarter-rate FP64 operation.  Every HIP file is compiled without
+# (a reciprocal-root seed and refinement steps, thirteen instructions) is
+# priced as one quarter-rate FP64 operation.  Every HIP file is compiled without
 # packed FP32 instructions.
 RATES_PUBLISHED = {"f32": 157.3 / 2, "f32_trans": 157.3 / 8, "f64": 78.6 / 2, "f64_sqrt": 78.6 / 8}
 

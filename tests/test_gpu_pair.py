@@ -195,6 +195,21 @@ def test_symmetry_bitwise(nA, nB):
         assert ab == ba
 
 
+def test_tiny_values_fp64():
+    """FP64 squared distances near 2^-800 take the square root's unscaled
+    path: the pair scaled by 2^-400 (values, times and lambda; homogeneity
+    keeps the exact result at 2^-400 times the unscaled one) against the
+    oracle on the same scaled inputs, and against 2^-400 times the GPU's
+    unscaled result."""
+    c = synth.random_pair(61, 62, 700, 900, 3, irregular=True, nu=0.02, lam=0.6, p=2.0)
+    s = 2.0 ** -400
+    want = oracle.twed(c.A * s, c.TA * s, c.B * s, c.TB * s, c.nu, c.lam * s, c.p)
+    got = gpu_twed(c.A * s, c.TA * s, c.B * s, c.TB * s, c.nu, c.lam * s, c.p, "f64")
+    assert abs(got - want) <= 1e-12 * abs(want), (got, want)
+    base = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f64")
+    assert abs(got - base * s) <= 1e-12 * abs(base * s), (got, base * s)
+
+
 def test_identity_is_zero():
     c = synth.single_pair_3d(5000)
     for prec in ("f64", "f32", "f32_acc64"):
