@@ -150,7 +150,7 @@ def parse():
     ap.add_argument("--knn-queries", type=int, default=10_000, help="k-NN queries timed")
     ap.add_argument("--knn-truth", type=int, default=1000,
                     help="queries given exhaustive ground truth (recall sample)")
-    ap.add_argument("--knn-train-steps", type=int, default=40000, help="training steps (2,048 pairs each)")
+    ap.add_argument("--knn-train-steps", type=int, default=80000, help="training steps (2,048 pairs each)")
     ap.add_argument("--knn-schedule", choices=("cosine", "constant"), default="cosine",
                     help="learning-rate schedule of the embedding training")
     ap.add_argument("--knn-anchors", type=int, default=4096,
@@ -271,8 +271,8 @@ def knn_bench(args, torch, tw, synth, dev, time_steps):
 
     curve = {}
     chosen = None
-    for c in (200, 400, 800, 1600, 3200, 4000, 4800, 5600, 6400, 7200, 8000, 9600, 11200, 12800, 16000, 19200, 25600, 38400,
-              51200):
+    for c in (200, 400, 800, 1600, 3200, 4000, 4400, 4800, 5200, 5600, 6000, 6400, 7200, 8000, 9600, 11200, 12800, 16000,
+              19200, 25600, 38400, 51200):
         c = min(c, args.knn_db)
         curve[c] = recall(c)
         log(f"knn: recall@10 with {c} candidates: {curve[c]:.4f}")
