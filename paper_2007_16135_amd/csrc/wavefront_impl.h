@@ -241,19 +241,53 @@ __device__ __forceinline__ void sweep_strip(GroupShared<AT, G> &sh, int w, int g
     const int in_mask = in_lds ? kRing - 1 : kWindow - 1;
     Pair2<AT> *const out_ring = out_lds ? &sh.ring[w < G - 1 ? w : 0][0] : &sh.out_stage[0];
 
+    // The next global window is fetched ahead when it is already published:
+    // its flag is read at the start of the window's second-to-last sub-chunk
+    // (the load completes behind that sub-chunk's steps), checked at the last
+    // one, and the window's rows are loaded there into registers, to be
+    // staged in LDS at the next window's start (their latency, too, hides
+    // behind a sub-chunk).  Otherwise the window start waits for the flag.
+    // (Single-strip groups, where every strip hands over through global
+    // memory, wait at each window start: fetching ahead there kept the
+    // window's rows in scratch memory.)
+    constexpr bool kAheadFetch = G > 1;
+    const int q_last = (kWindow >> sub_shift) - 1;
+    uint32_t ahead_flag = 0;
+    bool ahead = false;
+    Pair2<AT> ahead_rows{};
     for (int t0 = 0; t0 < T_run; t0 += kSub) {
         const int q = (t0 >> sub_shift) & ((kWindow >> sub_shift) - 1);  // sub-chunk within the window
         const int wb = t0 - q * kSub;                          // window start
         const int steps = T_run - t0 < kSub ? T_run - t0 : kSub;
+        const bool flagged = !TILE || s > 0;  // a tile's left column is there from the start
         if (in_global && q == 0) {
-            if (!TILE || s > 0) {  // a tile's left column is there from the start
-                const uint32_t need = (uint32_t)(t0 + kWindow < nA ? t0 + kWindow : nA);
-                wait_progress<false>(in_flag, need, err);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (ahead) {
+                sh.in_stage[lane] = ahead_rows;
+            } else {
+                if (flagged) {
+                    const uint32_t need = (uint32_t)(t0 + kWindow < nA ? t0 + kWindow : nA);
+                    wait_progress<false>(in_flag, need, err);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+                // rows t0 + 1 .. t0 + 64 of the boundary: lane l's row to slot l
+                const int rr = t0 + 1 + lane < nA ? t0 + 1 + lane : nA;
+                sh.in_stage[lane] = in_slot[rr];
             }
-            // rows t0 + 1 .. t0 + 64 of the boundary: lane l's row to slot l
-            const int rr = t0 + 1 + lane < nA ? t0 + 1 + lane : nA;
-            sh.in_stage[lane] = in_slot[rr];
+            ahead = false;
+        }
+        // (the flag's value is taken wave-uniform only where it is used, so
+        // the wave does not wait for the load where it is issued)
+        if (kAheadFetch && in_global && flagged && q_last > 0 && q == q_last - 1)
+            ahead_flag = __hip_atomic_load(in_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (kAheadFetch && in_global && q == q_last && wb + kWindow < T_run) {
+            const int nb0 = wb + kWindow;  // the next window's start
+            const uint32_t need = (uint32_t)(nb0 + kWindow < nA ? nb0 + kWindow : nA);
+            if (!flagged || (q_last > 0 && wave_uniform(ahead_flag) >= need)) {
+                if (flagged) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const int rr = nb0 + 1 + lane < nA ? nb0 + 1 + lane : nA;
+                ahead_rows = in_slot[rr];
+                ahead = true;
+            }
         }
         if (in_lds) {
             // the rows this sub-chunk reads, t0 + 1 .. t0 + kSub, are in the ring

@@ -298,6 +298,24 @@ def test_strip_groups_bitwise(prec, monkeypatch):
             assert v == ref, (prec, k, g, v, ref)
 
 
+@pytest.mark.parametrize("sub", ["8", "32"])
+def test_handoff_intervals_bitwise(sub, monkeypatch):
+    """In-group hand-over every 8 or 32 rows (TWED_WAVEFRONT_SUB), which also
+    moves where groups of several strips fetch the next global window ahead
+    (the window's second-to-last and last sub-chunks; with 32-row sub-chunks
+    only a tile's given left column is fetched ahead): every strip width and
+    group size agrees to the bit with the per-diagonal sweep."""
+    c = synth.random_pair(43, 44, 1400, 64 * 13 - 5, 3, irregular=True, nu=0.02, lam=0.6, p=2.0)
+    ref = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f64", algo="diagonal")
+    monkeypatch.setenv("TWED_WAVEFRONT_SUB", sub)
+    for k in (1, 2, 4):
+        for g in ("1", "4", "8"):
+            monkeypatch.setenv("TWED_WAVEFRONT_GROUP", g)
+            say(f"hand-over every {sub} rows K={k} G={g}")
+            v = gpu_twed(c.A, c.TA, c.B, c.TB, c.nu, c.lam, c.p, "f64", algo="wavefront", strip_k=k)
+            assert v == ref, (sub, k, g, v, ref)
+
+
 def test_strip_groups_long_pair_vs_oracle(monkeypatch):
     """A pair long enough for many LDS sub-chunks and global windows, in
     groups of 8, against the FP64 oracle (FP32 costs with FP64 accumulators)."""
