@@ -443,8 +443,8 @@ def cpu_all_cores(pairs, synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
-                                   "this build (see the design notes on sharding)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the library has no "
+                                   "multi-GPU path (column shards are swept one GPU at a time)", "n_gpus": args.gpus}))
         return 2
 
     import torch

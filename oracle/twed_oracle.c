@@ -29,8 +29,7 @@
  *                    DP[i-1][j-1] + mat(i, j))
  *     TWED     = DP[nA][nB]                                         (step 6)
  *
- * Readings where the printed text is garbled (each one is listed with its
- * reason in the design notes of the repository):
+ * Readings taken where the printed formulas are garbled:
  *   - the match term compares sample values (not consecutive differences),
  *     and includes the point cost of the cell;
  *   - the time term of the match pairs TA with TB at the column index;

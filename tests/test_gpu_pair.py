@@ -102,7 +102,7 @@ FAST = [c for c in ALGOS if c["algo"] != "diagonal"] or ALGOS  # sweep used for 
 
 def test_report_switched_off_sweeps():
     if OFF:
-        pytest.skip(f"switched off in this build: {OFF}")
+        pytest.skip(f"sweeps switched off in the library: {OFF}")
 
 
 @pytest.mark.parametrize("cfg", ALL_ALGOS, ids=lambda c: f"{c['algo']}{c.get('strip_k', '')}")
