@@ -263,7 +263,7 @@ typedef enum {
 
 /* One pair.  Errors: TWED_ERR_INVALID for an unknown kind, null pointers or
  * empty series; TWED_ERR_UNSUPPORTED for dim != 1 with EDIT / LCS, another
- * precision, strip_k other than 0, 1 or 8, or series >= 2^31;
+ * precision, strip_k other than 0, 1, 2 or 8, or series >= 2^31;
  * TWED_ERR_WORKSPACE if ws_bytes < twed_dp_workspace_size(...). */
 size_t twed_dp_workspace_size(int32_t kind, int64_t nA, int64_t nB, const twed_params *prm);
 

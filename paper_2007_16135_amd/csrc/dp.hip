@@ -14,7 +14,7 @@ namespace {
 
 // Strip widths and group sizes compiled for the sibling recurrences.
 template <int DIMT, int K>
-constexpr bool kDpCompiled = (K == 1 || K == 8) && kStripCompiled<DIMT, K>;
+constexpr bool kDpCompiled = (K == 1 || K == 2 || K == 8) && kStripCompiled<DIMT, K>;
 
 template <int REC, int DIMT>
 constexpr bool kDpDim = REC == kRecDtw || DIMT == 1;
@@ -64,6 +64,7 @@ hipError_t by_config(int rec, Prec prec, const CostParams &cp, int K, int G, Fn 
                 };
                 switch (K) {
                 case 1: return withK.template operator()<1>();
+                case 2: return withK.template operator()<2>();
                 case 8: return withK.template operator()<8>();
                 default: return hipErrorInvalidValue;
                 }

@@ -76,7 +76,7 @@ Sweep tile_sweep(int rec, int strip_k, int64_t nB, Prec prec, const CostParams &
     } else {
         const int64_t want = (int64_t)simds() * 3 / 4;
         for (int k : {8, 4, 2}) {
-            if (sib && k != 8) continue;
+            if (sib && k == 4) continue;
             const int64_t strips = (nB + 64 * k - 1) / (64 * k);
             if (strips >= want && sweep_scratch(rec, dirs, prec, cp, k, 1) == 0) {
                 K = k;
@@ -410,8 +410,8 @@ twed_status check_dp(int32_t kind, const twed_params *prm, Prec *prec)
     if (rec_of(kind) < 0) return fail(TWED_ERR_INVALID, "unknown twed_dp_kind");
     if (kind != TWED_DP_DTW && prm->dim != 1)
         return fail(TWED_ERR_UNSUPPORTED, "edit distance and LCS compare 1-D samples (dim = 1)");
-    if (!(prm->strip_k == 0 || prm->strip_k == 1 || prm->strip_k == 8))
-        return fail(TWED_ERR_UNSUPPORTED, "twed_dp takes strip_k 0, 1 or 8");
+    if (!(prm->strip_k == 0 || prm->strip_k == 1 || prm->strip_k == 2 || prm->strip_k == 8))
+        return fail(TWED_ERR_UNSUPPORTED, "twed_dp takes strip_k 0, 1, 2 or 8");
     if (!tile_prec(prm, prec)) return fail(TWED_ERR_UNSUPPORTED, "twed_dp takes TWED_F64 or TWED_F32_ACC64");
     return TWED_OK;
 }

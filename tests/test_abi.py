@@ -335,7 +335,7 @@ def test_dp_host_checks(L):
     assert dp(2, n=0) == INVALID
     assert dp(3, p=tw.make_params(dim=2)) == UNSUPPORTED
     assert dp(1, p=tw.make_params(precision="f32")) == UNSUPPORTED
-    assert dp(1, p=tw.make_params(strip_k=2)) == UNSUPPORTED
+    assert dp(1, p=tw.make_params(strip_k=4)) == UNSUPPORTED
     assert dp(1) == WORKSPACE
     assert L.twed_dp_path(2, FAKE, 10, FAKE, 10, c.byref(prm1), -1, FAKE, FAKE, FAKE, None, 0, None) == INVALID
     assert L.twed_dp_path(2, FAKE, 10, FAKE, 10, c.byref(prm1), 0, FAKE, None, FAKE, None, 0, None) == INVALID

@@ -43,7 +43,7 @@ def test_edit_and_lcs_exact(prec):
     for nA, nB, alph in ((1, 1, 2), (1, 50, 3), (37, 1, 3), (200, 170, 4), (1500, 1300, 4), (3000, 2100, 20),
                          (64, 64, 2), (65, 640, 5)):
         a, b = tokens(rng, nA, alph), tokens(rng, nB, alph)
-        for strip_k in (0, 1, 8):
+        for strip_k in (0, 1, 2, 8):
             say(f"edit/lcs {nA}x{nB} alphabet {alph} {prec} K={strip_k}")
             e = float(tw.twed_dp("edit", dev(a, prec), dev(b, prec), precision=prec, strip_k=strip_k).item())
             l = float(tw.twed_dp("lcs", dev(a, prec), dev(b, prec), precision=prec, strip_k=strip_k).item())
@@ -62,9 +62,10 @@ def test_dtw_vs_oracle(prec, dim, p):
         if prec != "f64":
             A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
         want = orc.dtw(A, B, p)
-        say(f"dtw {nA}x{nB} dim{dim} p{p} {prec}")
-        got = float(tw.twed_dp("dtw", dev(A, prec), dev(B, prec), p=p, precision=prec).item())
-        assert abs(got - want) <= (1e-12 if prec == "f64" else 1e-6) * want
+        for strip_k in (0, 1, 2):
+            say(f"dtw {nA}x{nB} dim{dim} p{p} {prec} K={strip_k}")
+            got = float(tw.twed_dp("dtw", dev(A, prec), dev(B, prec), p=p, precision=prec, strip_k=strip_k).item())
+            assert abs(got - want) <= (1e-12 if prec == "f64" else 1e-6) * want
 
 
 def _check_path(P, nA, nB, free_edges):
