@@ -110,22 +110,31 @@ def test_dp_paths():
 
 
 def test_dp_paths_long_and_wide_strips():
-    """A DTW path whose forward sweep uses strips of eight columns (a wide
-    pair) and blocks of 256; an edit path of 3000 x 2500 tokens."""
+    """DTW paths whose forward sweeps use strips of eight and of two columns
+    (blocks of 256); an edit path of 3000 x 2500 tokens; an LCS path swept in
+    strips of two columns."""
     rng = np.random.default_rng(12)
     orc = oracle.get()
     nA, nB = 3000, 2500
     A = rng.standard_normal((nA, 1)).cumsum(0)
     B = rng.standard_normal((nB, 1)).cumsum(0)
-    say("dtw path 3000x2500 strip_k 8")
-    v, path = tw.twed_dp_path("dtw", dev(A, "f64"), dev(B, "f64"), p=1.0, block=256, strip_k=8)
-    P = path.cpu().numpy()
-    _check_path(P, nA, nB, False)
     want = orc.dtw(A, B, 1.0)
-    assert abs(float(v.item()) - want) <= 1e-12 * want
-    cost = sum(abs(A[i - 1, 0] - B[j - 1, 0]) for i, j in P[1:])
-    assert abs(cost - want) <= 1e-10 * want
+    for strip_k in (8, 2):
+        say(f"dtw path 3000x2500 strip_k {strip_k}")
+        v, path = tw.twed_dp_path("dtw", dev(A, "f64"), dev(B, "f64"), p=1.0, block=256, strip_k=strip_k)
+        P = path.cpu().numpy()
+        _check_path(P, nA, nB, False)
+        assert abs(float(v.item()) - want) <= 1e-12 * want
+        cost = sum(abs(A[i - 1, 0] - B[j - 1, 0]) for i, j in P[1:])
+        assert abs(cost - want) <= 1e-10 * want
     a, b = tokens(rng, nA, 6), tokens(rng, nB, 6)
+    say("lcs path 3000x2500 strip_k 2")
+    v, path = tw.twed_dp_path("lcs", dev(a, "f64"), dev(b, "f64"), block=512, strip_k=2)
+    P = path.cpu().numpy()
+    _check_path(P, nA, nB, True)
+    steps = [(i1, j1) for (i0, j0), (i1, j1) in zip(P[:-1], P[1:]) if i1 - i0 == 1 and j1 - j0 == 1]
+    assert all(a[i - 1] == b[j - 1] for i, j in steps)
+    assert len(steps) == float(v.item()) == orc.lcs(a, b)
     say("edit path 3000x2500")
     v, path = tw.twed_dp_path("edit", dev(a, "f32_acc64"), dev(b, "f32_acc64"), precision="f32_acc64", block=512)
     P = path.cpu().numpy()
