@@ -121,8 +121,8 @@ int tile_max_workers(Prec prec, const CostParams &cp, int K, int G);
 // the inputs or set to the +inf pad); launched after every tile sweep.
 hipError_t launch_tile_edges(int64_t nA, int64_t nB, const TileArgs &t, hipStream_t st);
 // The tile sweep on a sibling recurrence (dp.hip; rec: 1 DTW, 2 edit
-// distance, 3 indel distance), strips of K = 1 or 8 columns per lane, groups
-// of G = 1 or 8 strips; other configurations return hipErrorInvalidValue /
+// distance, 3 indel distance), strips of K = 1, 2 or 8 columns per lane,
+// groups of G = 1 or 8 strips; other configurations return hipErrorInvalidValue /
 // (size_t)-1 / 0.
 hipError_t launch_dp(int rec, Prec prec, const CostParams &cp, int K, const WavefrontArgs &a, const TileArgs &t,
                      hipStream_t st);
